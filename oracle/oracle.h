@@ -1,0 +1,62 @@
+/*
+ * Oracle interface (test infrastructure only; see rketd1d.c).
+ */
+#ifndef FDTD_ORACLE_H
+#define FDTD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_BC_MUR1 = 0, OR_BC_CPML = 1, OR_BC_PEC = 2, OR_BC_PERIODIC = 3 };
+
+typedef struct {
+    int64_t n;                 /* E nodes 0..n-1; H nodes at k+1/2, k = 0..n-2 */
+    double dz, dt;             /* m, s */
+    const double *wp2;         /* [n] plasma frequency squared, rad^2/s^2 */
+    const double *nu;          /* [n] collision frequency, 1/s */
+    int32_t bc;
+    int32_t scheme;            /* 0 consistent eq.(11)+(12), 1 printed eq.(13), 2 eq.(9) */
+    int64_t cpml_cells;
+    double cpml_m;             /* grading order; <= 0 means 3 */
+    double cpml_sigma_max;     /* <= 0 means 0.8 (m+1)/(eta0 dz) */
+    int64_t src_cell;          /* < 0: no source */
+    double src_tau, src_t0, src_amp;
+    int32_t n_probes;
+    int32_t n_freqs;
+    const int64_t *probe_cells;
+    const double *freqs;       /* Hz */
+} or1d_problem;
+
+typedef struct {
+    double *E;                 /* [n] */
+    double *H;                 /* [n] (entry n-1 only for periodic) */
+    double *J;                 /* [n] */
+    double *psiE, *psiH;       /* [n] CPML auxiliaries (may be NULL unless CPML) */
+    double *Xre, *Xim;         /* [n_probes][n_freqs] running DFT */
+    int64_t step;              /* time index of E on entry / exit */
+} or1d_state;
+
+double or_c0(void);
+double or_eps0(void);
+double or_mu0(void);
+void or_phi(double x, double *a, double *phi1, double *phi2);
+void or_coeffs(int64_t n, const double *wp2, const double *nu, double dt,
+               double dz, int scheme, double *out);
+double or_source(double t, double tau, double t0, double amp);
+void or_twiddle(double f, double dt, int64_t m, double *c, double *s);
+void or_dft_accumulate(int64_t count, const double *samples, int64_t m0,
+                       int n_freqs, const double *freqs, double dt,
+                       double *Xre, double *Xim);
+int or1d_check(const or1d_problem *pb);
+int or1d_step(const or1d_problem *pb, or1d_state *st, int64_t nsteps);
+int or1d_adjoint_step(const or1d_problem *pb, double *lE, double *lH, double *lJ);
+int or1d_adjoint_r2(const or1d_problem *pb, int64_t nsteps, int32_t probe,
+                    const double *xv_re, const double *xv_im, double *loss,
+                    double *grad, double *X);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
