@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the 1D RKETD-FDTD plasma hot path on one MI355X.
+
+One bench "step" is one full run of the plain workload: 2^24 cells x 20000
+time steps (H-curl, E-curl minus J, ETD2 J advance, source, CPML ends, probe
+DFT), seeded synthetic plasma (sinusoidal wp^2 profile over the middle half,
+per-cell nu).  Inputs are resident in HBM before timing; each run() replays a
+captured HIP graph.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--precision f32|f64] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Mcell-updates/s & %HBM roofline (plain vs batched vs adjoint) at stated "
+          "|R|,|T| error")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_node(precision: str, plasma: bool) -> int:
+    """What one pass must move per node: read and write E, H (and J on plasma
+    nodes) once, plus the two FP64 material words (wp2, nu) on plasma nodes."""
+    es = 8 if precision == "f64" else 4
+    return (2 * 3 * es + 16) if plasma else 2 * 2 * es
+
+
+def run_precision(p, precision, T, K, W, tune):
+    import torch
+    from paper_1709_00821_amd.plasma import FdtdPlasma
+    h = FdtdPlasma(p, precision=precision, exec="tiled", **tune)
+    log(f"bench: {precision} tile_cells={h.desc.tile_cells} steps_per_pass={h.desc.steps_per_pass}"
+        f" workspace {h.workspace_bytes / 2**30:.2f} GiB")
+    for i in range(W):
+        h.run(T)
+        h.synchronize()
+        log(f"bench: warmup {i + 1}/{W} done")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(h.stream)
+    for i in range(K):
+        h.run(T)
+    ev1.record(h.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    X = h.spectra()[0]
+    log(f"bench: {precision} timed {K} runs: {ms / K:.2f} ms/run")
+    # per-launch durations on the handle's stream (HIP events inside the library)
+    prof_steps = min(T, 4000)
+    h.run(0)
+    prof = h.profile(prof_steps)
+    h.close()
+    return ms / K, X, prof
+
+
+def roofline(prof, precision):
+    """Dominant kernel: achieved = algorithmic bytes per launch (bytes per node
+    x nodes the launch advances, as the library reports) / mean launch time."""
+    name, (ms_tot, calls, units) = max(prof.items(), key=lambda kv: kv[1][0])
+    per = algorithmic_bytes_per_node(precision, name in ("tiled_plasma", "tiled_cpml", "resident",
+                                                         "step_h_e"))
+    bytes_per_launch = per * units / calls
+    avg_s = ms_tot / calls / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 2),
+            "launches": calls}
+
+
+def cpu_baseline(p, steps):
+    import oracle
+    log(f"bench: cpu baseline: oracle on the full {p.n}-cell grid for {steps} steps")
+    t0 = time.perf_counter()
+    oracle.run(p, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(p.n * steps / dt / 1e6, 2), "unit": "Mcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"full {p.n}-cell grid, {steps} steps (of {p.steps}), serial FP64, "
+                      f"{dt:.1f} s incl. coefficient build"}
+
+
+def oracle_spectra_lightcone(p, T):
+    """Exact oracle spectra of the full grid: outside the source's light cone
+    the fields stay exactly zero for T steps, so a trimmed grid suffices."""
+    import oracle
+    from paper_1709_00821_amd import workloads as W
+    lo, hi = W.light_cone(p, T)
+    wp2 = p.wp2[lo:hi].copy()
+    wp2[0] = wp2[-1] = 0.0
+    q = p.copy(n=hi - lo, wp2=wp2, nu=p.nu[lo:hi].copy(), src_cell=p.src_cell - lo,
+               probes=p.probes - lo, bc="pec", cpml_cells=0)
+    return oracle.run(q, T)["X"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--cells", type=int, default=1 << 24)
+    ap.add_argument("--time-steps", type=int, default=20000)
+    ap.add_argument("--tile-cells", type=int, default=0)
+    ap.add_argument("--steps-per-pass", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the method's independent grids would shard by cell ranges with a halo exchange, "
+              f"not built here)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd import tune as TU
+
+    T = args.time_steps
+    log(f"bench: building the {args.cells}-cell workload")
+    p = W.large_c2(n=args.cells, steps=T)
+    results = {}
+    for prec in ([args.precision] + ([] if args.no_fp64 else
+                                     [x for x in ("f64",) if x != args.precision])):
+        tune = TU.pick(prec, p.n, tile_cells=args.tile_cells, steps_per_pass=args.steps_per_pass)
+        ms, X, prof = run_precision(p, prec, T, args.steps, args.warmup, tune)
+        results[prec] = (ms, X, prof, tune)
+
+    ms, X, prof, tune = results[args.precision]
+    cells = p.n
+    value = cells * T / (ms / 1e3) / 1e6
+    rl = roofline(prof, args.precision)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"1D plain RKETD-FDTD, {cells} cells x {T} steps, CPML 32, "
+                               f"seeded sinusoidal wp2 on the middle half, per-cell nu",
+                   "cells": cells, "time_steps": T, "exec": "tiled",
+                   "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"],
+                   "fields": args.precision, "coefficients_dft": "f64"},
+        "roofline": rl,
+        "single_step_bound_mcells": round(HBM_PEAK_GBS * 1e9 / (
+            0.5 * algorithmic_bytes_per_node(args.precision, True)
+            + 0.5 * algorithmic_bytes_per_node(args.precision, False)) / 1e6, 1),
+        "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "nodes": v[2]}
+                    for k, v in prof.items()},
+    }
+    for prec, (ms2, X2, prof2, tune2) in results.items():
+        if prec == args.precision:
+            continue
+        out[prec] = {"value": round(cells * T / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(ms2, 3),
+                     "roofline": roofline(prof2, prec),
+                     "tile_cells": tune2["tile_cells"], "steps_per_pass": tune2["steps_per_pass"]}
+    if not args.no_check:
+        log("bench: oracle spectra on the source's light cone (exact)")
+        t0 = time.perf_counter()
+        Xo = oracle_spectra_lightcone(p, T)
+        acc = {}
+        for prec, r in results.items():
+            acc[prec] = float(np.max(np.abs(r[1] - Xo)) / np.max(np.abs(Xo)))
+        out["accuracy"] = {"spectra_rel_err_vs_fp64_oracle": acc,
+                           "oracle_seconds": round(time.perf_counter() - t0, 1)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * fdtd_plasma — RKETD-FDTD time stepping of electromagnetic waves in an
+ * unmagnetized (Drude) plasma, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Xiong et al., "The Electromagnetic Waves Propagation in Unmagnetized
+ * Plasma Media Using Parallelized FDTD", section II):
+ *   - Yee grid in 1D, eqs.(4)-(6): Ex on integer nodes k = 0..n-1, Hy on half
+ *     nodes k+1/2 (k = 0..n-2), the polarization current Jx with Ex;
+ *   - H update, eq.(14); E update from eqs.(11) and (12) solved together
+ *     (the consistent form of eq.(13)); J update by the second-order
+ *     exponential time differencing of eq.(11), whose exp(-nu dt) fractions
+ *     are evaluated in FP64;
+ *   - a Gaussian-derivative soft source, eq.(15), added after the E update;
+ *   - absorbing ends (section III uses PML; first-order Mur and a CPML here);
+ *   - a running DFT at probe nodes standing in for the FFT of section IV-B:
+ *       X(f) = sum_{m >= 1} E^m[p] dt exp(-j 2 pi f m dt)   (FP64 always).
+ *
+ * All calls return an int status: FDTD_OK (0) or a negative FDTD_E_* code.
+ * On error, fdtd_plasma_last_error() returns a thread-local message.  No C++
+ * exception crosses this interface.  A handle is not thread-safe: one host
+ * thread at a time.
+ */
+#ifndef FDTD_PLASMA_H
+#define FDTD_PLASMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_plasma fdtd_plasma;     /* opaque handle */
+
+enum {
+    FDTD_OK = 0,
+    FDTD_E_INVALID = -1,      /* a descriptor field or argument is out of range */
+    FDTD_E_UNSTABLE = -2,     /* Courant number c dt/dz above 1 */
+    FDTD_E_WORKSPACE = -3,    /* caller workspace too small or misaligned */
+    FDTD_E_DEVICE = -4,       /* a HIP runtime call failed (message has the HIP error) */
+    FDTD_E_STATE = -5,        /* call out of order (e.g. adjoint before a checkpointed run) */
+    FDTD_E_NONFINITE = -6,    /* a NaN/Inf reached a probe spectrum */
+    FDTD_E_UNSUPPORTED = -7   /* valid physics this build does not implement on the GPU */
+};
+
+enum { FDTD_F64 = 0, FDTD_F32 = 1 };
+
+/* Ends of every grid.  MUR1: first-order Mur at nodes 0 and n-1.  CPML: a
+ * convolutional PML of cpml_cells nodes at each end (kappa = 1, alpha = 0,
+ * sigma = sigma_max (depth/cpml_cells)^m) backed by PEC.  PEC: E = 0 at the
+ * end nodes. */
+enum { FDTD_BC_MUR1 = 0, FDTD_BC_CPML = 1, FDTD_BC_PEC = 2 };
+
+/* CONSISTENT: eqs.(11)+(12) solved for E^{n+1} (all terms divided by
+ * D = 1 + (wp dt)^2 phi2/2).  PAPER_EQ13: eq.(13) exactly as printed (only
+ * the E^n term carries 1/D).  ETD1: the first-order current update eq.(9). */
+enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 = 2 };
+
+/* How the time loop is executed (results agree bit for bit across modes):
+ * STEP:     two launches per time step (H, then E/J/source/ends/probes);
+ * TILED:    temporal blocking, steps_per_pass steps per launch on register
+ *           tiles of tile_cells nodes with halo recompute, ping-pong buffers;
+ * RESIDENT: one persistent launch; each workgroup keeps whole grids in
+ *           registers for the entire run (short grids, e.g. batches of slabs);
+ * AUTO:     RESIDENT when every grid fits a workgroup, else TILED. */
+enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RESIDENT = 3 };
+
+/* flags */
+#define FDTD_FLAG_CHECKPOINT 0x1   /* run() stores sqrt(T)-spaced checkpoints for the adjoint */
+
+typedef struct {
+    uint32_t struct_size;        /* sizeof(fdtd_plasma_desc) */
+    int32_t precision;           /* FDTD_F64 | FDTD_F32 (E, H, J storage and curl arithmetic) */
+    int32_t scheme;              /* FDTD_SCHEME_* */
+    int32_t bc;                  /* FDTD_BC_* */
+    int32_t exec;                /* FDTD_EXEC_* */
+    int32_t flags;               /* FDTD_FLAG_* */
+    int64_t batch;               /* number of independent 1D grids, >= 1 */
+    const int64_t *cells;        /* host [batch]: E nodes per grid, >= 3 */
+    double dz;                   /* m, > 0 */
+    double dt;                   /* s, > 0, c dt/dz <= 1 */
+    const double *wp2;           /* host [sum(cells)]: plasma frequency^2 per node, rad^2/s^2, >= 0;
+                                    0 at each grid's two end nodes and inside CPML layers */
+    const double *nu;            /* host [sum(cells)]: collision frequency per node, 1/s, >= 0 */
+    const int64_t *src_cell;     /* host [batch]: source node in 1..n-2, or -1 for none */
+    double src_tau, src_t0, src_amp;   /* eq.(15): s(t) = amp (t-t0) exp(-(t-t0)^2/(2 tau^2)) */
+    int32_t n_probes;            /* probes per grid, >= 1 */
+    int32_t n_freqs;             /* DFT frequencies, >= 1 */
+    const int64_t *probe_cells;  /* host [batch][n_probes]: nodes in 0..n-1 */
+    const double *freqs_hz;      /* host [n_freqs] */
+    int32_t cpml_cells;          /* CPML thickness in nodes (bc = CPML) */
+    int32_t tile_cells;          /* TILED: nodes per register tile (64*C); 0 = default */
+    double cpml_m;               /* CPML grading order; <= 0 means 3 */
+    double cpml_sigma_max;       /* <= 0 means 0.8 (m+1)/(eta0 dz) */
+    int32_t steps_per_pass;      /* TILED: time steps per launch (halo depth); 0 = default */
+    int32_t reserved0;
+    void *stream;                /* hipStream_t for every launch and copy; NULL = null stream */
+} fdtd_plasma_desc;
+
+/*
+ * Device bytes the handle needs for this descriptor (state, ping-pong
+ * buffers, plasma parameters, probe samples, DFT accumulators, checkpoints).
+ * The descriptor is validated as for create.
+ */
+int fdtd_plasma_workspace_bytes(const fdtd_plasma_desc *desc, size_t *bytes);
+
+/*
+ * Validate the descriptor, lay out the workspace, copy the host arrays to the
+ * device (on desc->stream) and zero the state.  Host arrays are borrowed only
+ * for the duration of the call.  dev_workspace (256-byte aligned device
+ * memory of at least fdtd_plasma_workspace_bytes) stays owned by the caller
+ * and must outlive the handle; NULL makes the library allocate and own it.
+ * On failure *out is NULL.
+ */
+int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace,
+                       size_t workspace_bytes, fdtd_plasma **out);
+
+/*
+ * Advance every grid by nsteps (>= 0) time steps, asynchronously on the
+ * handle's stream.  step(a) followed by step(b) gives bit-for-bit the same
+ * state and spectra as step(a + b).
+ */
+int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps);
+
+/*
+ * Reset fields, currents and spectra to zero at step 0, then advance nsteps,
+ * replaying a HIP graph captured on the first call with this nsteps.  With
+ * FDTD_FLAG_CHECKPOINT the run also stores the forward checkpoints used by
+ * fdtd_plasma_grad_r2.
+ */
+int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps);
+
+/*
+ * Copy the running DFT to host arrays re, im of [batch][n_probes][n_freqs]
+ * doubles, waiting for the stream.  FDTD_E_STATE before any step,
+ * FDTD_E_NONFINITE if any value is NaN or Inf (the values are still copied).
+ */
+int fdtd_plasma_probe_spectra(fdtd_plasma *h, double *re, double *im);
+
+/*
+ * Copy one grid's state to host arrays (doubles, waiting for the stream):
+ * E[n], H[n-1] (H at k+1/2), J[n] in A/m^2 (any pointer may be NULL).
+ */
+int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, double *J);
+
+/* Steps taken since create or the last run(). */
+int fdtd_plasma_steps_done(fdtd_plasma *h, int64_t *steps);
+
+/*
+ * Reflection-loss gradient by the discrete adjoint (sub-steps transposed in
+ * reverse order, forward states recomputed from sqrt(T) checkpoints).
+ * For every grid b:  L_b = sum_f |(X_b(f) - xref_b(f)) / xref_b(f)|^2  with X_b
+ * the spectrum at probe `probe` after nsteps, and grad[off_b + k] = dL_b/d wp2
+ * at node k.  xref_re/xref_im: host [batch][n_freqs] (the plasma-free
+ * reference spectra); loss: host [batch]; grad: host [sum(cells)].  Runs
+ * the forward pass itself (the handle's state afterwards is that of run()).
+ * Requires scheme CONSISTENT and MUR1 or PEC ends.
+ */
+int fdtd_plasma_grad_r2(fdtd_plasma *h, int64_t nsteps, int32_t probe,
+                        const double *xref_re, const double *xref_im,
+                        double *loss, double *grad);
+
+/*
+ * Per-kernel timing of nsteps eager steps from the current state (which they
+ * advance), with HIP events on the handle's stream around every launch.
+ * Host outputs: names char[max][32]; ms_total, calls, units [max] where
+ * units sums, over the launches, the grid nodes each launch advanced (the
+ * unit algorithmic bytes are counted in).  *count: distinct kernel groups.
+ */
+int fdtd_plasma_profile(fdtd_plasma *h, int64_t nsteps, int32_t max, char *names,
+                        double *ms_total, int64_t *calls, int64_t *units, int32_t *count);
+
+/* Release the handle (NULL is accepted).  Waits for the stream; does not
+ * free a caller-owned workspace. */
+int fdtd_plasma_destroy(fdtd_plasma *h);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char *fdtd_plasma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_PLASMA_H */

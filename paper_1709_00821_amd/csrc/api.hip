@@ -1,0 +1,853 @@
+// C-ABI of the fdtd_plasma library: validation, workspace layout, host->device
+// copies, time-loop orchestration (per-step, tiled, resident), graph capture,
+// probe spectra.  Every step of the method runs in the HIP kernels; the host
+// side only builds index tables and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd_plasma.h"
+#include "internal.h"
+
+using namespace fdtdp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(FDTD_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kAlign = 256;
+constexpr int64_t kNodePad = 64;   // grid offsets are multiples of 64 nodes
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Workspace carve-out: a list of (offset, bytes) regions.
+struct Layout {
+    int64_t total = 0;
+    int64_t take(int64_t bytes)
+    {
+        const int64_t o = total;
+        total += round_up(std::max<int64_t>(bytes, 16), kAlign);
+        return o;
+    }
+};
+
+struct Defaults {
+    int tile_cells;
+    int steps_per_pass;
+};
+
+}  // namespace
+
+struct fdtd_plasma {
+    fdtd_plasma_desc d;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool owns_ws = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    // host copies
+    std::vector<int64_t> cells, off, src, probe;
+    std::vector<double> freqs;
+    int64_t nodes = 0;        // padded node count
+    int64_t batch = 0;
+    int P = 0, F = 0, SB = 0;
+    int esize = 8;            // bytes per field value
+
+    // device pointers into the workspace
+    int64_t *d_off = nullptr, *d_n = nullptr, *d_src = nullptr, *d_probe = nullptr;
+    double *d_wp2 = nullptr, *d_nu = nullptr, *d_freqs = nullptr, *d_samp = nullptr,
+           *d_cpml = nullptr;
+    double2 *d_X = nullptr, *d_Xtmp = nullptr, *d_tw = nullptr;
+    void *d_E[2] = {nullptr, nullptr}, *d_H[2] = {nullptr, nullptr}, *d_J[2] = {nullptr, nullptr};
+    void *d_psiE[2] = {nullptr, nullptr}, *d_psiH[2] = {nullptr, nullptr};
+    int64_t state_bytes = 0, psi_bytes = 0;
+
+    // tiled executor
+    std::vector<Tile> tiles_host;
+    Tile *d_tiles = nullptr;
+    int64_t ntiles[3] = {0, 0, 0};
+    int64_t tile_first[3] = {0, 0, 0};
+    int tileC = 8, Kh = 16;
+
+    // resident executor
+    ResidentSlot *d_slots = nullptr;
+    int64_t nbins = 0;
+    int resC = 8, resWaves = 8;
+
+    int exec = FDTD_EXEC_STEP;
+
+    // time-loop state
+    int cur = 0;
+    int64_t steps = 0;        // time index of the state
+    int64_t win_base = 0;     // samples of m in (win_base, win_base + SB] are buffered
+
+    std::map<int64_t, hipGraphExec_t> graphs;
+    bool poisoned = false;
+
+    // per-launch timing (fdtd_plasma_profile)
+    struct ProfMark {
+        const char *name;
+        hipEvent_t a, b;
+        int64_t units;        // output nodes the launch group advances
+    };
+    int64_t class_nodes[3] = {0, 0, 0};   // output nodes per tile class
+    int64_t real_nodes = 0;
+    bool profiling = false;
+    std::vector<ProfMark> marks;
+
+    Grids grids() const
+    {
+        Grids g;
+        g.off = d_off;
+        g.n = d_n;
+        g.src = d_src;
+        g.probe = d_probe;
+        g.wp2 = d_wp2;
+        g.nu = d_nu;
+        g.samp = d_samp;
+        g.batch = batch;
+        g.P = P;
+        g.SB = SB;
+        g.scheme = d.scheme;
+        g.bc = d.bc;
+        g.cpmlP = d.bc == FDTD_BC_CPML ? d.cpml_cells : 0;
+        g.dt = d.dt;
+        g.dz = d.dz;
+        g.ch = d.dt / (mu0() * d.dz);
+        g.ce = d.dt / (kEps0 * d.dz);
+        const double S = kC0 * d.dt / d.dz;
+        g.cm = (S - 1.0) / (S + 1.0);
+        g.src_tau = d.src_tau;
+        g.src_t0 = d.src_t0;
+        g.src_amp = d.src_amp;
+        g.cpml = d_cpml;
+        return g;
+    }
+
+    template <typename T>
+    State<T> state()
+    {
+        State<T> s;
+        for (int i = 0; i < 2; ++i) {
+            s.E[i] = (T *)d_E[i];
+            s.H[i] = (T *)d_H[i];
+            s.J[i] = (T *)d_J[i];
+            s.psiE[i] = (T *)d_psiE[i];
+            s.psiH[i] = (T *)d_psiH[i];
+        }
+        return s;
+    }
+};
+
+namespace {
+
+int validate(const fdtd_plasma_desc *d)
+{
+    if (!d) return fail(FDTD_E_INVALID, "descriptor is NULL");
+    if (d->struct_size != sizeof(fdtd_plasma_desc))
+        return fail(FDTD_E_INVALID, "struct_size %u != %zu (header/library mismatch)",
+                    d->struct_size, sizeof(fdtd_plasma_desc));
+    if (d->precision != FDTD_F64 && d->precision != FDTD_F32)
+        return fail(FDTD_E_INVALID, "precision %d", d->precision);
+    if (d->scheme < 0 || d->scheme > 2) return fail(FDTD_E_INVALID, "scheme %d", d->scheme);
+    if (d->bc < 0 || d->bc > 2) return fail(FDTD_E_INVALID, "bc %d", d->bc);
+    if (d->exec < 0 || d->exec > 3) return fail(FDTD_E_INVALID, "exec %d", d->exec);
+    if (d->batch < 1) return fail(FDTD_E_INVALID, "batch %lld < 1", (long long)d->batch);
+    if (!d->cells || !d->wp2 || !d->nu || !d->src_cell || !d->probe_cells || !d->freqs_hz)
+        return fail(FDTD_E_INVALID, "a host array pointer is NULL");
+    if (!(d->dz > 0.0) || !(d->dt > 0.0) || !std::isfinite(d->dz) || !std::isfinite(d->dt))
+        return fail(FDTD_E_INVALID, "dz and dt must be positive and finite");
+    if (kC0 * d->dt / d->dz > 1.0)
+        return fail(FDTD_E_UNSTABLE, "Courant number c dt/dz = %.6g exceeds 1", kC0 * d->dt / d->dz);
+    if (d->n_probes < 1 || d->n_freqs < 1)
+        return fail(FDTD_E_INVALID, "need n_probes >= 1 and n_freqs >= 1");
+    if (d->n_probes > 64) return fail(FDTD_E_INVALID, "n_probes %d > 64", d->n_probes);
+    if (!(std::isfinite(d->src_tau) && d->src_tau > 0 && std::isfinite(d->src_t0) &&
+          std::isfinite(d->src_amp)))
+        return fail(FDTD_E_INVALID, "source parameters must be finite with tau > 0");
+    for (int f = 0; f < d->n_freqs; ++f)
+        if (!std::isfinite(d->freqs_hz[f])) return fail(FDTD_E_INVALID, "freqs_hz[%d] not finite", f);
+    if (d->bc == FDTD_BC_CPML && d->cpml_cells < 1)
+        return fail(FDTD_E_INVALID, "cpml_cells must be >= 1 with CPML ends");
+    int64_t o = 0;
+    for (int64_t b = 0; b < d->batch; ++b) {
+        const int64_t n = d->cells[b];
+        if (n < 3 || n > (int64_t)1 << 31)
+            return fail(FDTD_E_INVALID, "grid %lld: cells %lld out of [3, 2^31]", (long long)b,
+                        (long long)n);
+        if (d->bc == FDTD_BC_CPML && 2 * (int64_t)d->cpml_cells >= n)
+            return fail(FDTD_E_INVALID, "grid %lld: CPML of %d nodes per end needs more than %lld nodes",
+                        (long long)b, d->cpml_cells, (long long)n);
+        const int64_t s = d->src_cell[b];
+        if (s != -1 && (s < 1 || s > n - 2))
+            return fail(FDTD_E_INVALID, "grid %lld: source node %lld outside [1, n-2]", (long long)b,
+                        (long long)s);
+        for (int p = 0; p < d->n_probes; ++p) {
+            const int64_t q = d->probe_cells[b * d->n_probes + p];
+            if (q < 0 || q >= n)
+                return fail(FDTD_E_INVALID, "grid %lld: probe %d node %lld outside [0, n)",
+                            (long long)b, p, (long long)q);
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            const double w = d->wp2[o + k], v = d->nu[o + k];
+            if (!(w >= 0.0) || !std::isfinite(w) || !(v >= 0.0) || !std::isfinite(v))
+                return fail(FDTD_E_INVALID, "grid %lld node %lld: wp2 and nu must be finite and >= 0",
+                            (long long)b, (long long)k);
+            if (w != 0.0 && (k == 0 || k == n - 1))
+                return fail(FDTD_E_INVALID, "grid %lld: wp2 must be 0 at the end nodes", (long long)b);
+            if (w != 0.0 && d->bc == FDTD_BC_CPML &&
+                (k < d->cpml_cells || k > n - 1 - d->cpml_cells))
+                return fail(FDTD_E_UNSUPPORTED, "grid %lld node %lld: plasma inside the CPML layer",
+                            (long long)b, (long long)k);
+        }
+        o += n;
+    }
+    if (d->tile_cells != 0 && (d->tile_cells % 256 != 0 || d->tile_cells < 256 || d->tile_cells > 1024))
+        return fail(FDTD_E_INVALID, "tile_cells %d: must be 0, 256, 512, 768 or 1024", d->tile_cells);
+    if (d->steps_per_pass != 0 && (d->steps_per_pass < 4 || d->steps_per_pass % 4 != 0 ||
+                                   d->steps_per_pass > 64))
+        return fail(FDTD_E_INVALID, "steps_per_pass %d: must be 0 or a multiple of 4 in [4, 64]",
+                    d->steps_per_pass);
+    return FDTD_OK;
+}
+
+struct Plan {
+    Layout L;
+    int64_t o_off = 0, o_n = 0, o_src = 0, o_probe = 0, o_wp2 = 0, o_nu = 0, o_freqs = 0, o_samp = 0,
+            o_X = 0, o_Xtmp = 0, o_tw = 0, o_cpml = 0;
+    int64_t o_E[2] = {0, 0}, o_H[2] = {0, 0}, o_J[2] = {0, 0}, o_psiE[2] = {0, 0}, o_psiH[2] = {0, 0};
+    int64_t o_tiles = 0, o_slots = 0;
+    int64_t nodes = 0, state_bytes = 0, psi_bytes = 0;
+    int SB = 0;
+    std::vector<int64_t> off;
+    std::vector<Tile> tiles;
+    int64_t ntiles[3] = {0, 0, 0}, tile_first[3] = {0, 0, 0};
+    std::vector<ResidentSlot> slots;
+    int64_t nbins = 0;
+    int exec = 0, tileC = 8, Kh = 16, resC = 8, resWaves = 8;
+};
+
+// Tile tables for the temporally blocked executor: per grid, outputs of width
+// W = tile - 2 Kh; held span [out_lo - Kh, out_hi + Kh) clipped to the grid.
+void build_tiles(const fdtd_plasma_desc *d, Plan &p)
+{
+    const int L = p.tileC * 64;
+    const int W = L - 2 * p.Kh;
+    std::vector<Tile> cls[3];
+    int64_t o = 0;
+    for (int64_t b = 0; b < d->batch; ++b) {
+        const int64_t n = d->cells[b];
+        for (int64_t out = 0; out < n; out += W) {
+            Tile t{};
+            t.grid = (int32_t)b;
+            t.out_lo = (int32_t)out;
+            t.out_hi = (int32_t)std::min<int64_t>(n, out + W);
+            t.lo = (int32_t)std::max<int64_t>(0, out - p.Kh);
+            t.hi = (int32_t)std::min<int64_t>(n, (int64_t)t.lo + L);
+            int fl = 0;
+            if (t.lo == 0) fl |= TILE_LEFT_END;
+            if (t.hi == n) fl |= TILE_RIGHT_END;
+            const int64_t s = d->src_cell[b];
+            if (s >= t.lo && s < t.hi) fl |= TILE_SOURCE;
+            for (int q = 0; q < d->n_probes; ++q) {
+                const int64_t pc = d->probe_cells[b * d->n_probes + q];
+                if (pc >= t.out_lo && pc < t.out_hi) fl |= TILE_PROBE;
+            }
+            for (int64_t k = t.lo; k < t.hi; ++k)
+                if (d->wp2[o + k] != 0.0) { fl |= TILE_PLASMA; break; }
+            if (d->bc == FDTD_BC_CPML &&
+                (t.lo < d->cpml_cells + 1 || t.hi > n - 2 - d->cpml_cells))
+                fl |= TILE_CPML;
+            t.flags = fl;
+            const int k = (fl & TILE_CPML) ? 2 : (fl & TILE_PLASMA) ? 1 : 0;
+            cls[k].push_back(t);
+        }
+        o += n;
+    }
+    p.tiles.clear();
+    for (int k = 0; k < 3; ++k) {
+        p.tile_first[k] = (int64_t)p.tiles.size();
+        p.ntiles[k] = (int64_t)cls[k].size();
+        p.tiles.insert(p.tiles.end(), cls[k].begin(), cls[k].end());
+    }
+}
+
+// Resident bins: grids packed first-fit-decreasing into workgroups of
+// resWaves waves, each grid on ceil(n / (64 C)) consecutive waves.
+bool build_bins(const fdtd_plasma_desc *d, Plan &p)
+{
+    const int64_t per_wave = 64LL * p.resC;
+    std::vector<std::pair<int64_t, int64_t>> need;  // (waves, grid)
+    std::vector<int> shift(d->batch, 0);
+    for (int64_t b = 0; b < d->batch; ++b) {
+        const int64_t n = d->cells[b];
+        shift[b] = ((n - 1) % per_wave == 0) ? 1 : 0;
+        const int64_t w = (n + shift[b] + per_wave - 1) / per_wave;
+        if (w > p.resWaves) return false;
+        need.push_back({w, b});
+    }
+    std::stable_sort(need.begin(), need.end(),
+                     [](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+                         return a.first > b.first;
+                     });
+    std::vector<int> used;                          // waves used per bin
+    std::vector<std::vector<ResidentSlot>> bins;
+    for (auto &nw : need) {
+        size_t j = 0;
+        for (; j < bins.size(); ++j)
+            if (used[j] + nw.first <= p.resWaves) break;
+        if (j == bins.size()) {
+            bins.emplace_back();
+            used.push_back(0);
+        }
+        ResidentSlot s{};
+        s.grid = (int32_t)nw.second;
+        s.first_wave = used[j];
+        s.nwaves = (int32_t)nw.first;
+        s.shift = shift[nw.second];
+        used[j] += (int)nw.first;
+        bins[j].push_back(s);
+    }
+    // flatten: one entry per wave of each bin (grid -1 marks an idle wave)
+    p.slots.clear();
+    for (size_t j = 0; j < bins.size(); ++j) {
+        std::vector<ResidentSlot> row(p.resWaves, ResidentSlot{-1, 0, 0, 0});
+        for (auto &s : bins[j])
+            for (int w = 0; w < s.nwaves; ++w) {
+                row[s.first_wave + w] = s;
+            }
+        p.slots.insert(p.slots.end(), row.begin(), row.end());
+    }
+    p.nbins = (int64_t)bins.size();
+    return true;
+}
+
+int plan(const fdtd_plasma_desc *d, Plan &p)
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    const int es = d->precision == FDTD_F64 ? 8 : 4;
+    const int P = d->n_probes, F = d->n_freqs;
+    p.off.resize(d->batch + 1);
+    int64_t o = 0;
+    for (int64_t b = 0; b < d->batch; ++b) {
+        p.off[b] = o;
+        o += round_up(d->cells[b], kNodePad) + kNodePad;
+    }
+    p.off[d->batch] = o;
+    p.nodes = o;
+    p.state_bytes = o * es;
+    p.psi_bytes = d->bc == FDTD_BC_CPML ? d->batch * 2 * d->cpml_cells * es : 16;
+
+    // executor choice
+    p.tileC = d->tile_cells ? d->tile_cells / 64 : (es == 8 ? 8 : 8);
+    p.Kh = d->steps_per_pass ? d->steps_per_pass : 16;
+    p.resC = 8;
+    p.resWaves = 8;   // 512-thread workgroups keep the FP64 coefficients in registers without spills
+    p.exec = d->exec;
+    if (p.exec == FDTD_EXEC_RESIDENT && d->bc == FDTD_BC_CPML)
+        return fail(FDTD_E_UNSUPPORTED, "the resident executor has no CPML ends");
+    if (p.exec == FDTD_EXEC_AUTO && d->bc == FDTD_BC_CPML) p.exec = FDTD_EXEC_TILED;
+    if (p.exec == FDTD_EXEC_RESIDENT || p.exec == FDTD_EXEC_AUTO) {
+        const bool ok = build_bins(d, p);
+        if (!ok && p.exec == FDTD_EXEC_RESIDENT)
+            return fail(FDTD_E_INVALID, "a grid exceeds %d nodes, the resident limit",
+                        64 * p.resC * p.resWaves);
+        if (!ok) p.exec = FDTD_EXEC_TILED;
+        else p.exec = FDTD_EXEC_RESIDENT;
+    }
+    if (p.exec == FDTD_EXEC_TILED) {
+        if (p.tileC * 64 <= 2 * p.Kh + 64)
+            return fail(FDTD_E_INVALID, "tile of %d nodes too small for halo %d", p.tileC * 64, p.Kh);
+        build_tiles(d, p);
+    }
+    if (p.exec != FDTD_EXEC_RESIDENT) { p.slots.clear(); p.nbins = 0; }
+
+    // sample window: up to 16384 steps, at most ~256 MiB of samples
+    {
+        int64_t sb = ((int64_t)1 << 28) / (8 * d->batch * P);
+        sb = std::max<int64_t>(64, std::min<int64_t>(16384, sb));
+        p.SB = (int)(sb / 64 * 64);
+    }
+
+    Layout &L = p.L;
+    L = Layout();
+    p.o_off = L.take(8 * (d->batch + 1));
+    p.o_n = L.take(8 * d->batch);
+    p.o_src = L.take(8 * d->batch);
+    p.o_probe = L.take(8 * d->batch * P);
+    p.o_freqs = L.take(8 * F);
+    p.o_wp2 = L.take(8 * p.nodes);
+    p.o_nu = L.take(8 * p.nodes);
+    p.o_samp = L.take(8 * d->batch * P * (int64_t)p.SB);
+    p.o_X = L.take(16 * d->batch * P * (int64_t)F);
+    p.o_Xtmp = L.take(16 * d->batch * P * (int64_t)F);
+    p.o_tw = L.take(16 * (int64_t)std::min(p.SB, kTwiddleChunk) * F);
+    p.o_cpml = L.take(8 * 4 * std::max(1, d->cpml_cells));
+    for (int i = 0; i < 2; ++i) {
+        p.o_E[i] = L.take(p.state_bytes);
+        p.o_H[i] = L.take(p.state_bytes);
+        p.o_J[i] = L.take(p.state_bytes);
+        p.o_psiE[i] = L.take(p.psi_bytes);
+        p.o_psiH[i] = L.take(p.psi_bytes);
+    }
+    p.o_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.tiles.size()));
+    p.o_slots = L.take((int64_t)sizeof(ResidentSlot) * std::max<size_t>(1, p.slots.size()));
+    return FDTD_OK;
+}
+
+template <typename T>
+void zero_state(fdtd_plasma *h)
+{
+    for (int i = 0; i < 2; ++i) {
+        launch_fill(h->d_E[i], round_up(h->state_bytes, 16), h->stream);
+        launch_fill(h->d_H[i], round_up(h->state_bytes, 16), h->stream);
+        launch_fill(h->d_J[i], round_up(h->state_bytes, 16), h->stream);
+        launch_fill(h->d_psiE[i], round_up(h->psi_bytes, 16), h->stream);
+        launch_fill(h->d_psiH[i], round_up(h->psi_bytes, 16), h->stream);
+    }
+    launch_fill(h->d_X, 16 * h->batch * h->P * (int64_t)h->F, h->stream);
+}
+
+void reset(fdtd_plasma *h)
+{
+    if (h->esize == 8) zero_state<double>(h); else zero_state<float>(h);
+    h->cur = 0;
+    h->steps = 0;
+    h->win_base = 0;
+}
+
+// Events around one launch group while profiling (no-ops otherwise).
+void prof_begin(fdtd_plasma *h, const char *name, int64_t units)
+{
+    if (!h->profiling) return;
+    fdtd_plasma::ProfMark m{name, nullptr, nullptr, units};
+    if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return;
+    (void)hipEventRecord(m.a, h->stream);
+    h->marks.push_back(m);
+}
+
+void prof_end(fdtd_plasma *h)
+{
+    if (!h->profiling || h->marks.empty()) return;
+    (void)hipEventRecord(h->marks.back().b, h->stream);
+}
+
+// Fold the full sample window into X.
+void flush(fdtd_plasma *h)
+{
+    const int count = (int)(h->steps - h->win_base);
+    prof_begin(h, "dft_flush", 0);
+    launch_dft(h->grids(), h->d_freqs, h->F, h->win_base + 1, count, h->d_tw, h->d_X,
+               h->batch * h->P, h->stream);
+    prof_end(h);
+    h->win_base = h->steps;
+}
+
+template <typename T>
+int advance_t(fdtd_plasma *h, int64_t nsteps)
+{
+    const Grids g = h->grids();
+    State<T> s = h->state<T>();
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int slot = (int)(h->steps - h->win_base);
+        int64_t room = h->SB - slot;
+        int64_t k;
+        static const char *kTiledNames[3] = {"tiled_vacuum", "tiled_plasma", "tiled_cpml"};
+        if (h->exec == FDTD_EXEC_STEP) {
+            k = 1;
+            prof_begin(h, "step_h_e", h->real_nodes);
+            launch_step<T>(g, s, h->cur, h->nodes, h->steps + 1, slot, h->stream);
+            prof_end(h);
+        } else if (h->exec == FDTD_EXEC_TILED) {
+            k = std::min<int64_t>(std::min<int64_t>(left, room), h->Kh);
+            for (int c = 0; c < 3; ++c)
+                if (h->ntiles[c]) {
+                    prof_begin(h, kTiledNames[c], h->class_nodes[c]);
+                    launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c,
+                                    h->tileC, (int)k, h->steps, slot, h->stream);
+                    prof_end(h);
+                }
+        } else {
+            k = std::min<int64_t>(left, room);
+            prof_begin(h, "resident", h->real_nodes);
+            launch_resident<T>(g, s, h->cur, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k,
+                               h->steps, slot, h->stream);
+            prof_end(h);
+        }
+        if (h->exec != FDTD_EXEC_RESIDENT) h->cur ^= 1;
+        h->steps += k;
+        left -= k;
+        if (h->steps - h->win_base == h->SB) flush(h);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FDTD_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+int advance(fdtd_plasma *h, int64_t nsteps)
+{
+    return h->esize == 8 ? advance_t<double>(h, nsteps) : advance_t<float>(h, nsteps);
+}
+
+int check_handle(fdtd_plasma *h)
+{
+    if (!h) return fail(FDTD_E_INVALID, "handle is NULL");
+    if (h->poisoned) return fail(FDTD_E_STATE, "handle used after a device failure");
+    return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fdtd_plasma_last_error(void) { return g_last_error.c_str(); }
+
+int fdtd_plasma_workspace_bytes(const fdtd_plasma_desc *desc, size_t *bytes)
+{
+    if (!bytes) return fail(FDTD_E_INVALID, "bytes is NULL");
+    Plan p;
+    int rc = plan(desc, p);
+    if (rc) return rc;
+    *bytes = (size_t)p.L.total;
+    return FDTD_OK;
+}
+
+int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t workspace_bytes,
+                       fdtd_plasma **out)
+{
+    if (!out) return fail(FDTD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    Plan p;
+    int rc = plan(desc, p);
+    if (rc) return rc;
+    if (dev_workspace && workspace_bytes < (size_t)p.L.total)
+        return fail(FDTD_E_WORKSPACE, "workspace of %zu bytes < %lld needed", workspace_bytes,
+                    (long long)p.L.total);
+    if (dev_workspace && ((uintptr_t)dev_workspace % kAlign))
+        return fail(FDTD_E_WORKSPACE, "workspace not %lld-byte aligned", (long long)kAlign);
+
+    fdtd_plasma *h = new (std::nothrow) fdtd_plasma();
+    if (!h) return fail(FDTD_E_INVALID, "out of host memory");
+    h->d = *desc;
+    h->stream = (hipStream_t)desc->stream;
+    h->batch = desc->batch;
+    h->P = desc->n_probes;
+    h->F = desc->n_freqs;
+    h->SB = p.SB;
+    h->esize = desc->precision == FDTD_F64 ? 8 : 4;
+    h->nodes = p.nodes;
+    h->state_bytes = p.state_bytes;
+    h->psi_bytes = p.psi_bytes;
+    h->exec = p.exec;
+    h->tileC = p.tileC;
+    h->Kh = p.Kh;
+    h->resC = p.resC;
+    h->resWaves = p.resWaves;
+    h->nbins = p.nbins;
+    for (int k = 0; k < 3; ++k) {
+        h->ntiles[k] = p.ntiles[k];
+        h->tile_first[k] = p.tile_first[k];
+        for (int64_t t = 0; t < p.ntiles[k]; ++t) {
+            const Tile &tl = p.tiles[p.tile_first[k] + t];
+            h->class_nodes[k] += tl.out_hi - tl.out_lo;
+        }
+    }
+    for (int64_t b = 0; b < desc->batch; ++b) h->real_nodes += desc->cells[b];
+    h->cells.assign(desc->cells, desc->cells + desc->batch);
+    h->off = p.off;
+    h->src.assign(desc->src_cell, desc->src_cell + desc->batch);
+    h->probe.assign(desc->probe_cells, desc->probe_cells + desc->batch * desc->n_probes);
+    h->freqs.assign(desc->freqs_hz, desc->freqs_hz + desc->n_freqs);
+    h->d.cells = nullptr;
+    h->d.wp2 = h->d.nu = nullptr;
+    h->d.src_cell = h->d.probe_cells = nullptr;
+    h->d.freqs_hz = nullptr;
+
+    auto undo = [&](int code) {
+        if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+        delete h;
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return undo(fail(FDTD_E_DEVICE, "no HIP device"));
+    if (dev_workspace) {
+        h->ws = (char *)dev_workspace;
+        h->ws_bytes = workspace_bytes;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->ws, (size_t)p.L.total);
+        if (e != hipSuccess)
+            return undo(fail(FDTD_E_DEVICE, "hipMalloc(%lld) failed: %s", (long long)p.L.total,
+                             hipGetErrorString(e)));
+        h->owns_ws = true;
+        h->ws_bytes = (size_t)p.L.total;
+    }
+    char *w = h->ws;
+    h->d_off = (int64_t *)(w + p.o_off);
+    h->d_n = (int64_t *)(w + p.o_n);
+    h->d_src = (int64_t *)(w + p.o_src);
+    h->d_probe = (int64_t *)(w + p.o_probe);
+    h->d_freqs = (double *)(w + p.o_freqs);
+    h->d_wp2 = (double *)(w + p.o_wp2);
+    h->d_nu = (double *)(w + p.o_nu);
+    h->d_samp = (double *)(w + p.o_samp);
+    h->d_X = (double2 *)(w + p.o_X);
+    h->d_Xtmp = (double2 *)(w + p.o_Xtmp);
+    h->d_tw = (double2 *)(w + p.o_tw);
+    h->d_cpml = (double *)(w + p.o_cpml);
+    for (int i = 0; i < 2; ++i) {
+        h->d_E[i] = w + p.o_E[i];
+        h->d_H[i] = w + p.o_H[i];
+        h->d_J[i] = w + p.o_J[i];
+        h->d_psiE[i] = w + p.o_psiE[i];
+        h->d_psiH[i] = w + p.o_psiH[i];
+    }
+    h->d_tiles = (Tile *)(w + p.o_tiles);
+    h->d_slots = (ResidentSlot *)(w + p.o_slots);
+
+    // padded material arrays (zero in the padding)
+    std::vector<double> wp2(p.nodes, 0.0), nu(p.nodes, 0.0);
+    {
+        int64_t o = 0;
+        for (int64_t b = 0; b < desc->batch; ++b) {
+            std::memcpy(&wp2[p.off[b]], desc->wp2 + o, 8 * desc->cells[b]);
+            std::memcpy(&nu[p.off[b]], desc->nu + o, 8 * desc->cells[b]);
+            o += desc->cells[b];
+        }
+    }
+    hipStream_t st = h->stream;
+    auto H2D = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = H2D(h->d_off, p.off.data(), 8 * (desc->batch + 1));
+    if (e == hipSuccess) e = H2D(h->d_n, desc->cells, 8 * desc->batch);
+    if (e == hipSuccess) e = H2D(h->d_src, desc->src_cell, 8 * desc->batch);
+    if (e == hipSuccess) e = H2D(h->d_probe, desc->probe_cells, 8 * desc->batch * desc->n_probes);
+    if (e == hipSuccess) e = H2D(h->d_freqs, desc->freqs_hz, 8 * desc->n_freqs);
+    if (e == hipSuccess) e = H2D(h->d_wp2, wp2.data(), 8 * p.nodes);
+    if (e == hipSuccess) e = H2D(h->d_nu, nu.data(), 8 * p.nodes);
+    if (e == hipSuccess && !p.tiles.empty())
+        e = H2D(h->d_tiles, p.tiles.data(), sizeof(Tile) * p.tiles.size());
+    if (e == hipSuccess && !p.slots.empty())
+        e = H2D(h->d_slots, p.slots.data(), sizeof(ResidentSlot) * p.slots.size());
+    if (e != hipSuccess)
+        return undo(fail(FDTD_E_DEVICE, "host-to-device copy failed: %s", hipGetErrorString(e)));
+    if (desc->bc == FDTD_BC_CPML) {
+        const double m = desc->cpml_m > 0 ? desc->cpml_m : 3.0;
+        const double eta0 = std::sqrt(mu0() / kEps0);
+        const double smax = desc->cpml_sigma_max > 0 ? desc->cpml_sigma_max
+                                                     : 0.8 * (m + 1.0) / (eta0 * desc->dz);
+        launch_cpml_table(h->d_cpml, desc->cpml_cells, m, smax, desc->dt, st);
+    }
+    reset(h);
+    // the host staging vectors die with this scope: wait for the copies
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return undo(fail(FDTD_E_DEVICE, "create failed: %s", hipGetErrorString(e)));
+    *out = h;
+    return FDTD_OK;
+}
+
+int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(FDTD_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
+    return advance(h, nsteps);
+}
+
+int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(FDTD_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
+    if (h->stream == nullptr) {
+        // the legacy null stream cannot be captured: run eagerly
+        reset(h);
+        return advance(h, nsteps);
+    }
+    auto it = h->graphs.find(nsteps);
+    if (it == h->graphs.end()) {
+        // capture reset + the whole time loop once for this length
+        HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        reset(h);
+        rc = advance(h, nsteps);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(FDTD_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(FDTD_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        it = h->graphs.emplace(nsteps, exec).first;
+    } else {
+        // bookkeeping identical to what the captured launches did
+        h->cur = 0;
+        h->steps = 0;
+        h->win_base = 0;
+        int64_t left = nsteps;
+        while (left > 0) {
+            const int slot = (int)(h->steps - h->win_base);
+            const int64_t room = h->SB - slot;
+            int64_t k = h->exec == FDTD_EXEC_STEP ? 1
+                        : h->exec == FDTD_EXEC_TILED ? std::min<int64_t>(std::min<int64_t>(left, room), h->Kh)
+                                                     : std::min<int64_t>(left, room);
+            if (h->exec != FDTD_EXEC_RESIDENT) h->cur ^= 1;
+            h->steps += k;
+            left -= k;
+            if (h->steps - h->win_base == h->SB) h->win_base = h->steps;
+        }
+    }
+    HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    return FDTD_OK;
+}
+
+int fdtd_plasma_steps_done(fdtd_plasma *h, int64_t *steps)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!steps) return fail(FDTD_E_INVALID, "steps is NULL");
+    *steps = h->steps;
+    return FDTD_OK;
+}
+
+int fdtd_plasma_probe_spectra(fdtd_plasma *h, double *re, double *im)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!re || !im) return fail(FDTD_E_INVALID, "output pointer is NULL");
+    if (h->steps == 0) return fail(FDTD_E_STATE, "no step taken yet");
+    const int64_t rows = h->batch * h->P, nX = rows * h->F;
+    // X plus the partial window, without disturbing the running sums
+    HIP_TRY(hipMemcpyAsync(h->d_Xtmp, h->d_X, 16 * nX, hipMemcpyDeviceToDevice, h->stream));
+    const int count = (int)(h->steps - h->win_base);
+    launch_dft(h->grids(), h->d_freqs, h->F, h->win_base + 1, count, h->d_tw, h->d_Xtmp, rows,
+               h->stream);
+    std::vector<double2> X(nX);
+    HIP_TRY(hipMemcpyAsync(X.data(), h->d_Xtmp, 16 * nX, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    bool finite = true;
+    for (int64_t i = 0; i < nX; ++i) {
+        re[i] = X[i].x;
+        im[i] = X[i].y;
+        finite = finite && std::isfinite(X[i].x) && std::isfinite(X[i].y);
+    }
+    if (!finite) return fail(FDTD_E_NONFINITE, "a probe spectrum holds NaN or Inf");
+    return FDTD_OK;
+}
+
+int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, double *J)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (grid < 0 || grid >= h->batch) return fail(FDTD_E_INVALID, "grid %lld out of range", (long long)grid);
+    const int64_t n = h->cells[grid], o = h->off[grid];
+    const int es = h->esize;
+    std::vector<char> buf(n * es);
+    auto fetch = [&](void *base, double *dst, int64_t cnt) -> int {
+        if (!dst) return FDTD_OK;
+        HIP_TRY(hipMemcpyAsync(buf.data(), (char *)base + o * es, cnt * es, hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        for (int64_t k = 0; k < cnt; ++k)
+            dst[k] = es == 8 ? ((double *)buf.data())[k] : (double)((float *)buf.data())[k];
+        return FDTD_OK;
+    };
+    if ((rc = fetch(h->d_E[h->cur], E, n))) return rc;
+    if ((rc = fetch(h->d_H[h->cur], H, n - 1))) return rc;
+    if ((rc = fetch(h->d_J[h->cur], J, n))) return rc;
+    return FDTD_OK;
+}
+
+int fdtd_plasma_grad_r2(fdtd_plasma *h, int64_t nsteps, int32_t probe, const double *xref_re,
+                        const double *xref_im, double *loss, double *grad)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    (void)nsteps; (void)probe; (void)xref_re; (void)xref_im; (void)loss; (void)grad;
+    return fail(FDTD_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+int fdtd_plasma_profile(fdtd_plasma *h, int64_t nsteps, int32_t max, char *names, double *ms_total,
+                        int64_t *calls, int64_t *units, int32_t *count)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (nsteps < 0 || max < 1 || !names || !ms_total || !calls || !units || !count)
+        return fail(FDTD_E_INVALID, "profile: bad arguments");
+    h->profiling = true;
+    h->marks.clear();
+    rc = advance(h, nsteps);
+    h->profiling = false;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    std::vector<std::string> nm;
+    std::vector<double> ms;
+    std::vector<int64_t> cnt, un;
+    for (auto &m : h->marks) {
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, m.a, m.b);
+        size_t j = 0;
+        for (; j < nm.size(); ++j)
+            if (nm[j] == m.name) break;
+        if (j == nm.size()) { nm.push_back(m.name); ms.push_back(0.0); cnt.push_back(0); un.push_back(0); }
+        ms[j] += t;
+        cnt[j] += 1;
+        un[j] += m.units;
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    h->marks.clear();
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(FDTD_E_DEVICE, "profile: %s", hipGetErrorString(e));
+    const int nout = (int)std::min<size_t>(nm.size(), (size_t)max);
+    for (int j = 0; j < nout; ++j) {
+        std::memset(names + 32 * j, 0, 32);
+        std::strncpy(names + 32 * j, nm[j].c_str(), 31);
+        ms_total[j] = ms[j];
+        calls[j] = cnt[j];
+        units[j] = un[j];
+    }
+    *count = nout;
+    return FDTD_OK;
+}
+
+int fdtd_plasma_destroy(fdtd_plasma *h)
+{
+    if (!h) return FDTD_OK;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+    return FDTD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal interfaces between the host library (api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "physics.h"
+
+namespace fdtdp {
+
+// Device view of all grids of a handle (passed by value to kernels).
+struct Grids {
+    const int64_t *off;     // [batch] first node of grid b in the padded node arrays
+    const int64_t *n;       // [batch] nodes of grid b
+    const int64_t *src;     // [batch] source node or -1
+    const int64_t *probe;   // [batch * P] probe nodes
+    const double *wp2;      // [nodes] plasma frequency^2
+    const double *nu;       // [nodes] collision frequency
+    double *samp;           // [batch * P][SB] probe samples of the current window
+    int64_t batch;
+    int P;                  // probes per grid
+    int SB;                 // sample window length
+    int scheme;
+    int bc;                 // FDTD_BC_*
+    int cpmlP;              // CPML nodes per end (bc = CPML)
+    double dt, dz;
+    double ch;              // dt/(mu0 dz)
+    double ce;              // dt/(eps0 dz)
+    double cm;              // Mur coefficient (S-1)/(S+1)
+    double src_tau, src_t0, src_amp;
+    const double *cpml;     // [4][cpmlP]: bE(depth d+1), aE(d+1), bH(depth j+1/2), aH(j+1/2)
+};
+
+// State buffers of one precision.
+template <typename T>
+struct State {
+    T *E[2];
+    T *H[2];
+    T *J[2];
+    T *psiE[2];             // [batch][2][P]: left zone then right zone
+    T *psiH[2];
+};
+
+struct Launch {
+    hipStream_t stream;
+};
+
+// One tile of the temporally blocked kernel (node indices local to the grid).
+struct Tile {
+    int32_t grid;
+    int32_t lo;        // first node held
+    int32_t hi;        // one past the last node held (<= n)
+    int32_t out_lo;    // first node written back
+    int32_t out_hi;    // one past the last node written back
+    int32_t flags;     // TILE_* bits
+    int32_t pad0, pad1;
+};
+
+enum {
+    TILE_LEFT_END = 1,    // node 0 held
+    TILE_RIGHT_END = 2,   // node n-1 held
+    TILE_SOURCE = 4,      // the grid's source node held
+    TILE_PROBE = 8,       // a probe node among the written-back nodes
+    TILE_PLASMA = 16,     // some held node has wp2 > 0
+    TILE_CPML = 32        // some held node lies in a CPML layer
+};
+
+// One workgroup of the resident kernel: waves [w0, w1) of a bin hold grid g's
+// nodes [node0, node0 + waves*64*C).
+struct ResidentSlot {
+    int32_t grid;
+    int32_t first_wave;   // wave index (within the workgroup) holding node 0
+    int32_t nwaves;       // waves used by this grid
+    int32_t shift;        // 1: node k sits at position k+1 (keeps n-2, n-1 in one lane)
+};
+
+// Samples folded into the DFT per twiddle table (table: kTwiddleChunk x F).
+constexpr int kTwiddleChunk = 1024;
+
+// ---- kernel launchers (kernels1d.hip) ------------------------------------
+template <typename T>
+void launch_step(const Grids &g, State<T> &s, int cur, int64_t total_nodes, int64_t m,
+                 int slot, hipStream_t st);
+
+template <typename T>
+void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
+                  int klass, int C, int nsteps, int64_t m0, int slot0, hipStream_t st);
+
+template <typename T>
+void launch_resident(const Grids &g, State<T> &s, int cur, const ResidentSlot *slots,
+                     int64_t nbins, int waves_per_wg, int C, int nsteps, int64_t m0,
+                     int slot0, hipStream_t st);
+
+void launch_dft(const Grids &g, const double *freqs, int F, int64_t m_first, int count,
+                double2 *tw, double2 *X, int64_t rows, hipStream_t st);
+
+void launch_fill(void *p, int64_t bytes, hipStream_t st);
+
+void launch_cpml_table(double *tab, int P, double m, double smax, double dt, hipStream_t st);
+
+int resident_max_nodes(int C, int waves);
+
+}  // namespace fdtdp

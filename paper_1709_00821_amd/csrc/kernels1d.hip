@@ -1,0 +1,264 @@
+// 1D RKETD-FDTD kernels for gfx950: per-step reference kernels, the
+// temporally blocked register-tile kernel, probe DFT, setup helpers.
+// Every kernel advances nodes through the same per-node functions of
+// physics.h, so all execution modes agree bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace fdtdp {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int grid_of(const Grids &g, int64_t i)
+{
+    // largest b with off[b] <= i (off is increasing)
+    int64_t lo = 0, hi = g.batch - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (g.off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return (int)lo;
+}
+
+// Index into the compact CPML arrays [batch][2][P] and table slot for E node k
+// (returns -1 outside the layers; the PEC end nodes carry no psi).
+__device__ __forceinline__ int cpml_e_slot(int P, int64_t n, int64_t k, int &tab)
+{
+    if (k >= 1 && k < P) { tab = P - 1 - (int)k; return (int)k; }
+    if (k > n - 1 - P && k <= n - 2) {
+        const int d = (int)(k - (n - 1 - P));   // depth 1..P-1
+        tab = d - 1;
+        return P + (int)(k - (n - P));
+    }
+    return -1;
+}
+
+// Same for H node k (position k+1/2), k = 0..n-2.
+__device__ __forceinline__ int cpml_h_slot(int P, int64_t n, int64_t k, int &tab)
+{
+    if (k < P) { tab = P - 1 - (int)k; return (int)k; }      // depth P-k-1/2
+    if (k >= n - 1 - P && k <= n - 2) {
+        tab = (int)(k - (n - 1 - P));                         // depth j+1/2
+        return P + tab;
+    }
+    return -1;
+}
+
+// ------------------------------------------------------ per-step reference
+
+// H^{n+1/2} of every node, written to buffer nxt.
+template <typename T>
+__global__ void k_step_h(Grids g, State<T> s, int cur, int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int b = grid_of(g, i);
+    const int64_t off = g.off[b], n = g.n[b], k = i - off;
+    if (k > n - 2) return;
+    const int nxt = cur ^ 1;
+    const T *E = s.E[cur] + off;
+    const T dE = E[k + 1] - E[k];
+    T Hn;
+    if (g.bc == 1) {
+        int tab;
+        const int slot = cpml_h_slot(g.cpmlP, n, k, tab);
+        if (slot >= 0) {
+            const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
+            const T bH = (T)g.cpml[2 * g.cpmlP + tab], aH = (T)g.cpml[3 * g.cpmlP + tab];
+            const T psi = __builtin_fma(aH, dE, bH * s.psiH[cur][ps]);
+            s.psiH[nxt][ps] = psi;
+            Hn = __builtin_fma(-(T)g.ch, dE + psi, s.H[cur][off + k]);
+        } else {
+            Hn = h_update<T>(s.H[cur][off + k], E[k], E[k + 1], (T)g.ch);
+        }
+    } else {
+        Hn = h_update<T>(s.H[cur][off + k], E[k], E[k + 1], (T)g.ch);
+    }
+    s.H[nxt][off + k] = Hn;
+}
+
+// E^{n+1} (and J^{n+1}, psiE) of interior node k of grid b; H already at
+// n+1/2 in buffer nxt.  Returns the new E; writes J and psi when asked.
+template <typename T>
+__device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, int cur, int b,
+                                           int64_t off, int64_t n, int64_t k, int64_t m,
+                                           bool write)
+{
+    const int nxt = cur ^ 1;
+    const T *H = s.H[nxt] + off;
+    T curl = H[k] - H[k - 1];
+    if (g.bc == 1) {
+        int tab;
+        const int slot = cpml_e_slot(g.cpmlP, n, k, tab);
+        if (slot >= 0) {
+            const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
+            const T bE = (T)g.cpml[tab], aE = (T)g.cpml[g.cpmlP + tab];
+            const T psi = __builtin_fma(aE, curl, bE * s.psiE[cur][ps]);
+            if (write) s.psiE[nxt][ps] = psi;
+            curl = curl + psi;
+        }
+    }
+    const T Eo = s.E[cur][off + k];
+    const double wp2 = g.wp2[off + k];
+    T En;
+    Coef c;
+    if (wp2 != 0.0) {
+        c = node_coef(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
+        En = (T)e_update_plasma<T>(Eo, s.J[cur][off + k], curl, c);
+    } else {
+        En = e_update_vac<T>(Eo, curl, (T)g.ce);
+    }
+    if (k == g.src[b])
+        En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
+    if (write) {
+        s.J[nxt][off + k] = (wp2 != 0.0) ? (T)j_update<T>(s.J[cur][off + k], Eo, En, c) : (T)0;
+    }
+    return En;
+}
+
+// E^{n+1}, J^{n+1}, ends and probe samples; reads buffer cur, writes nxt.
+template <typename T>
+__global__ void k_step_e(Grids g, State<T> s, int cur, int64_t total, int64_t m, int slot)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int b = grid_of(g, i);
+    const int64_t off = g.off[b], n = g.n[b], k = i - off;
+    if (k >= n) return;
+    const int nxt = cur ^ 1;
+    T En;
+    if (k == 0 || k == n - 1) {
+        if (g.bc == 0) {  // first-order Mur: E0' = E1 + cm (E1' - E0)
+            const int64_t kn = (k == 0) ? 1 : n - 2;
+            const T Enb = step_interior<T>(g, s, cur, b, off, n, kn, m, false);
+            const T *E = s.E[cur] + off;
+            En = E[kn] + (T)g.cm * (Enb - E[k]);
+        } else {
+            En = (T)0;
+        }
+        s.J[nxt][off + k] = (T)0;
+    } else {
+        En = step_interior<T>(g, s, cur, b, off, n, k, m, true);
+    }
+    s.E[nxt][off + k] = En;
+    for (int p = 0; p < g.P; ++p)
+        if (g.probe[(int64_t)b * g.P + p] == k)
+            g.samp[((int64_t)b * g.P + p) * g.SB + slot] = (double)En;
+}
+
+template <typename T>
+void launch_step(const Grids &g, State<T> &s, int cur, int64_t total, int64_t m, int slot,
+                 hipStream_t st)
+{
+    const int bs = 256;
+    const unsigned nb = (unsigned)((total + bs - 1) / bs);
+    hipLaunchKernelGGL(k_step_h<T>, dim3(nb), dim3(bs), 0, st, g, s, cur, total);
+    hipLaunchKernelGGL(k_step_e<T>, dim3(nb), dim3(bs), 0, st, g, s, cur, total, m, slot);
+}
+
+template void launch_step<float>(const Grids &, State<float> &, int, int64_t, int64_t, int,
+                                 hipStream_t);
+template void launch_step<double>(const Grids &, State<double> &, int, int64_t, int64_t, int,
+                                  hipStream_t);
+
+// ------------------------------------------------------------------- DFT
+
+// tw[i][f] = dt e^{-j 2 pi f (m_first + i) dt} for i < count.
+__global__ void k_dft_twiddle(const double *freqs, int F, int64_t m_first, int count, double dt,
+                              double2 *tw)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)count * F) return;
+    const int i = (int)(t / F), f = (int)(t % F);
+    double re, im;
+    twiddle(freqs[f] * dt, dt, m_first + i, re, im);
+    tw[t] = make_double2(re, im);
+}
+
+// X[row][f] += sum_i samp[row][i] tw[i][f], summed in a fixed order: lanes of a
+// wave take interleaved sample blocks, then a fixed xor-shuffle tree.
+// One wave per (row, f); SPLIT lanes per output.
+__global__ __launch_bounds__(256) void k_dft_accum(const double *samp, int SB, int64_t rows, int F,
+                                                   int count, const double2 *tw, double2 *X)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= rows * F) return;
+    const int64_t row = wave / F;
+    const int f = (int)(wave % F);
+    const double *sp = samp + row * SB;
+    double ar = 0.0, ai = 0.0;
+    for (int i = lane; i < count; i += 64) {
+        const double v = sp[i];
+        const double2 w = tw[(int64_t)i * F + f];
+        ar = __builtin_fma(v, w.x, ar);
+        ai = __builtin_fma(v, w.y, ai);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        ar += __shfl_xor(ar, d, 64);
+        ai += __shfl_xor(ai, d, 64);
+    }
+    if (lane == 0) {
+        double2 x = X[row * F + f];
+        x.x += ar;
+        x.y += ai;
+        X[row * F + f] = x;
+    }
+}
+
+void launch_dft(const Grids &g, const double *freqs, int F, int64_t m_first, int count,
+                double2 *tw, double2 *X, int64_t rows, hipStream_t st)
+{
+    // twiddles for at most kTwiddleChunk samples at a time
+    for (int c0 = 0; c0 < count; c0 += kTwiddleChunk) {
+        const int cnt = count - c0 < kTwiddleChunk ? count - c0 : kTwiddleChunk;
+        const int64_t tot = (int64_t)cnt * F;
+        hipLaunchKernelGGL(k_dft_twiddle, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                           freqs, F, m_first + c0, cnt, g.dt, tw);
+        const int64_t waves = rows * F;
+        hipLaunchKernelGGL(k_dft_accum, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st,
+                           (const double *)(g.samp + c0), g.SB, rows, F, cnt, (const double2 *)tw, X);
+    }
+}
+
+// ----------------------------------------------------------------- setup
+
+__global__ void k_fill(uint4 *p, int64_t n16)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = i; j < n16; j += stride) p[j] = make_uint4(0, 0, 0, 0);
+}
+
+// Zero fill with a kernel (a graph-safe replacement for memset); bytes is a
+// multiple of 16 and p 16-byte aligned.
+void launch_fill(void *p, int64_t bytes, hipStream_t st)
+{
+    const int64_t n16 = bytes / 16;
+    if (n16 <= 0) return;
+    int64_t nb = (n16 + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, st, (uint4 *)p, n16);
+}
+
+__global__ void k_cpml_table(double *tab, int P, double m, double smax, double dt)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    double b, a;
+    cpml_ab((double)(j + 1), P, m, smax, dt, b, a);   // E node at depth j+1
+    tab[j] = b;
+    tab[P + j] = a;
+    cpml_ab((double)j + 0.5, P, m, smax, dt, b, a);   // H node at depth j+1/2
+    tab[2 * P + j] = b;
+    tab[3 * P + j] = a;
+}
+
+void launch_cpml_table(double *tab, int P, double m, double smax, double dt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cpml_table, dim3((P + 63) / 64), dim3(64), 0, st, tab, P, m, smax, dt);
+}
+
+}  // namespace fdtdp

@@ -1,0 +1,194 @@
+// Per-node physics of the 1D RKETD-FDTD plasma step, shared by every kernel of
+// the library so that all execution modes (per-step, temporally blocked,
+// resident) produce bit-identical results.  Host code uses the same inline
+// functions for setup tables.
+//
+// Paper, section II:
+//   eq.(14)  H^{n+1/2}(k+1/2) = H^{n-1/2}(k+1/2) - dt/(mu0 dz) [E^n(k+1) - E^n(k)]
+//   eq.(11)  J^{n+1} = e^{-nu dt} J^n + (1-e^{-nu dt})/nu eps0 wp^2 E^n
+//                     + (e^{-nu dt}-1+nu dt)/(nu^2 dt) eps0 wp^2 (E^{n+1} - E^n)
+//   eq.(12)  E^{n+1} = E^n - dt/(eps0 dz) [H(k+1/2) - H(k-1/2)] - dt/(2 eps0) (J^{n+1} + J^n)
+// Solving (11) and (12) together for E^{n+1} gives, with x = nu dt,
+//   a = e^{-x}, phi1 = (1-e^{-x})/x, phi2 = (e^{-x}-1+x)/x^2, w = (wp dt)^2,
+//   D = 1 + w phi2/2, CA = 1 - w phi1/(2D), CJ = dt (1+a)/(2 eps0 D),
+//   CH = dt/(eps0 dz D), b1 = eps0 wp^2 dt (phi1-phi2), b2 = eps0 wp^2 dt phi2:
+//   E^{n+1} = CA E^n - CJ J^n - CH curl H,   J^{n+1} = a J^n + b1 E^n + b2 E^{n+1}.
+// The printed eq.(13) keeps 1/D on the E^n term only (scheme PAPER_EQ13);
+// eq.(9) is the first-order variant (scheme ETD1: b1 = eps0 wp^2 dt phi1, b2 = 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdtdp {
+
+// SI constants (CODATA 2018 eps0; c exact); mu0 = 1/(eps0 c^2).
+constexpr double kC0 = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+__host__ __device__ inline double mu0() { return 1.0 / (kEps0 * kC0 * kC0); }
+
+struct Coef {
+    double CA, CJ, CH, a, b1, b2;
+};
+
+// phi-functions of the exponential integrator.  For x <= 0.5 the closed forms
+// cancel catastrophically (and divide by zero at nu = 0), so phi2 is summed
+// from its Taylor series sum_k (-x)^k/(k+2)! in Horner form; then
+// phi1 = 1 - x phi2 and a = 1 - x phi1 are exact identities with no
+// cancellation at small x.  Above 0.5 the closed forms are well conditioned.
+__host__ __device__ inline void phi_funcs(double x, double &a, double &p1, double &p2)
+{
+    if (x <= 0.5) {
+        // 1/(k+2)! for k = 16 .. 0 (truncation below 2.4e-21 at x = 0.5)
+        constexpr double inv[17] = {
+            1.0 / 6402373705728000.0,  // 1/18!
+            1.0 / 355687428096000.0,   // 1/17!
+            1.0 / 20922789888000.0,    // 1/16!
+            1.0 / 1307674368000.0,     // 1/15!
+            1.0 / 87178291200.0,       // 1/14!
+            1.0 / 6227020800.0,        // 1/13!
+            1.0 / 479001600.0,         // 1/12!
+            1.0 / 39916800.0,          // 1/11!
+            1.0 / 3628800.0,           // 1/10!
+            1.0 / 362880.0,            // 1/9!
+            1.0 / 40320.0,             // 1/8!
+            1.0 / 5040.0,              // 1/7!
+            1.0 / 720.0,               // 1/6!
+            1.0 / 120.0,               // 1/5!
+            1.0 / 24.0,                // 1/4!
+            1.0 / 6.0,                 // 1/3!
+            1.0 / 2.0};                // 1/2!
+        double s = inv[0];
+        for (int k = 1; k < 17; ++k) s = __builtin_fma(s, -x, inv[k]);
+        p2 = s;
+        p1 = __builtin_fma(-x, p2, 1.0);
+        a = __builtin_fma(-x, p1, 1.0);
+    } else {
+        a = exp(-x);
+        p1 = (1.0 - a) / x;
+        p2 = (a - 1.0 + x) / (x * x);
+    }
+}
+
+// Coefficients of one node.  In vacuum (wp2 = 0) this yields CA = 1, CJ = dt
+// (1+a)/(2 eps0), CH = dt/(eps0 dz), b1 = b2 = 0.
+__host__ __device__ inline Coef node_coef(double wp2, double nu, double dt, double dz, int scheme)
+{
+    double a, p1, p2;
+    phi_funcs(nu * dt, a, p1, p2);
+    const double w = wp2 * dt * dt;
+    Coef c;
+    c.a = a;
+    if (scheme == 2) {  // ETD1, eq.(9)
+        c.b1 = kEps0 * wp2 * dt * p1;
+        c.b2 = 0.0;
+        c.CA = 1.0 - 0.5 * w * p1;
+        c.CJ = dt * (1.0 + a) / (2.0 * kEps0);
+        c.CH = dt / (kEps0 * dz);
+        return c;
+    }
+    c.b1 = kEps0 * wp2 * dt * (p1 - p2);
+    c.b2 = kEps0 * wp2 * dt * p2;
+    const double D = 1.0 + 0.5 * w * p2;
+    c.CA = 1.0 - 0.5 * w * p1 / D;
+    if (scheme == 1) {  // eq.(13) as printed
+        c.CJ = dt * (1.0 + a) / (2.0 * kEps0);
+        c.CH = dt / (kEps0 * dz);
+    } else {
+        c.CJ = dt * (1.0 + a) / (2.0 * kEps0 * D);
+        c.CH = dt / (kEps0 * dz * D);
+    }
+    return c;
+}
+
+// d(coefficient)/d(wp2) for the consistent scheme (adjoint gradients).
+struct DCoef {
+    double dCA, dCJ, dCH, db1, db2;
+};
+
+__host__ __device__ inline DCoef node_dcoef(double wp2, double nu, double dt, double dz)
+{
+    double a, p1, p2;
+    phi_funcs(nu * dt, a, p1, p2);
+    const double D = 1.0 + 0.5 * wp2 * dt * dt * p2;
+    const double dD = 0.5 * dt * dt * p2;
+    const Coef c = node_coef(wp2, nu, dt, dz, 0);
+    DCoef d;
+    d.dCA = -(0.5 * dt * dt * p1) / (D * D);
+    d.dCJ = -c.CJ * dD / D;
+    d.dCH = -c.CH * dD / D;
+    d.db1 = kEps0 * dt * (p1 - p2);
+    d.db2 = kEps0 * dt * p2;
+    return d;
+}
+
+// eq.(15) soft source value at time t.
+__host__ __device__ inline double source_value(double t, double tau, double t0, double amp)
+{
+    const double u = t - t0;
+    return amp * u * exp(-(u * u) / (2.0 * tau * tau));
+}
+
+// DFT phase of sample m at frequency f: (f dt) m cycles, reduced exactly by the
+// nearest integer, times 2 pi.  The twiddle is dt e^{-j theta}.
+__host__ __device__ inline void twiddle(double fdt, double dt, int64_t m, double &re, double &im)
+{
+    double cyc = fdt * (double)m;
+    cyc = cyc - rint(cyc);
+    const double th = (2.0 * kPi) * cyc;
+    double s, c;
+    sincos(th, &s, &c);
+    re = dt * c;
+    im = -dt * s;
+}
+
+// CPML grading at a depth (in nodes, measured from the inner interface):
+// sigma = smax (depth/P)^m, b = exp(-sigma dt/eps0), a = b - 1 (kappa = 1, alpha = 0).
+__host__ __device__ inline void cpml_ab(double depth, int P, double m, double smax, double dt,
+                                        double &b, double &a)
+{
+    const double sigma = smax * pow(depth / (double)P, m);
+    b = exp(-sigma * dt / kEps0);
+    a = b - 1.0;
+}
+
+// ---- per-node updates (storage type T; plasma nodes computed in FP64) ----
+
+// Soft source: E + s, rounded once to the storage type.
+template <typename T>
+__device__ __forceinline__ T add_source(T E, double s)
+{
+    return (T)((double)E + s);
+}
+
+template <typename T>
+__device__ __forceinline__ T h_update(T H, T Eleft, T Eright, T ch)
+{
+    return __builtin_fma(-ch, Eright - Eleft, H);
+}
+
+// Vacuum node: CA = 1, J = 0, CH = dt/(eps0 dz).
+template <typename T>
+__device__ __forceinline__ T e_update_vac(T E, T curl, T ce)
+{
+    return __builtin_fma(-ce, curl, E);
+}
+
+// Plasma node: E_new = CA E - CJ J - CH curl, in FP64 whatever T is.
+template <typename T>
+__device__ __forceinline__ double e_update_plasma(T E, T J, T curl, const Coef &c)
+{
+    const double e = (double)E, j = (double)J, cu = (double)curl;
+    return __builtin_fma(-c.CH, cu, __builtin_fma(-c.CJ, j, c.CA * e));
+}
+
+// J_new = a J + b1 E_old + b2 E_new (FP64).
+template <typename T>
+__device__ __forceinline__ double j_update(T J, T Eold, T Enew, const Coef &c)
+{
+    return __builtin_fma(c.b2, (double)Enew, __builtin_fma(c.b1, (double)Eold, c.a * (double)J));
+}
+
+}  // namespace fdtdp

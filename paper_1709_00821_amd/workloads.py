@@ -187,8 +187,12 @@ def random_slab(rng: np.random.Generator, n: int, *, bc: str = "mur",
     dt = courant * dz / C0
     wpmax2 = (2 * math.pi * wpmax_ghz * GHZ) ** 2
     margin = max(2, cpml_cells + 1)
-    lo = int(rng.integers(margin, max(margin + 1, int(n * plasma_frac[0]))))
-    hi = int(rng.integers(max(lo + 1, int(n * plasma_frac[1])), n - margin))
+    if n - 2 * margin < 2:
+        raise ValueError("grid too short for its absorbing layers")
+    a = max(margin, min(int(n * plasma_frac[0]), n - margin - 2))
+    lo = int(rng.integers(margin, a + 1))
+    b = max(lo + 1, min(int(n * plasma_frac[1]), n - margin))
+    hi = int(rng.integers(b, n - margin + 1))
     wp2 = np.zeros(n)
     wp2[lo:hi] = rng.uniform(0.0, wpmax2, hi - lo)
     nu = rng.uniform(nu_ghz[0] * GHZ, nu_ghz[1] * GHZ, n)
