@@ -93,7 +93,8 @@ typedef struct {
     double cpml_m;               /* CPML grading order; <= 0 means 3 */
     double cpml_sigma_max;       /* <= 0 means 0.8 (m+1)/(eta0 dz) */
     int32_t steps_per_pass;      /* TILED: time steps per launch (halo depth); 0 = default */
-    int32_t reserved0;
+    int32_t checkpoint_steps;    /* with FDTD_FLAG_CHECKPOINT: longest run the checkpoint and
+                                    adjoint storage is sized for (>= 1) */
     void *stream;                /* hipStream_t for every launch and copy; NULL = null stream */
 } fdtd_plasma_desc;
 
@@ -147,14 +148,26 @@ int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, d
 int fdtd_plasma_steps_done(fdtd_plasma *h, int64_t *steps);
 
 /*
- * Reflection-loss gradient by the discrete adjoint (sub-steps transposed in
- * reverse order, forward states recomputed from sqrt(T) checkpoints).
- * For every grid b:  L_b = sum_f |(X_b(f) - xref_b(f)) / xref_b(f)|^2  with X_b
- * the spectrum at probe `probe` after nsteps, and grad[off_b + k] = dL_b/d wp2
- * at node k.  xref_re/xref_im: host [batch][n_freqs] (the plasma-free
- * reference spectra); loss: host [batch]; grad: host [sum(cells)].  Runs
- * the forward pass itself (the handle's state afterwards is that of run()).
- * Requires scheme CONSISTENT and MUR1 or PEC ends.
+ * Reflection loss of the current spectra, for every grid b:
+ *   L_b = sum_f |R_b(f)|^2,  R_b(f) = (X_b(f) - xref_b(f)) / xref_b(f),
+ * X_b the running DFT at probe `probe` (R is the two-run reflection
+ * coefficient when xref is the same probe in a plasma-free run).
+ * xref_re/xref_im: host [batch][n_freqs]; loss: host [batch].  Waits for
+ * the stream.  FDTD_E_STATE before any step.
+ */
+int fdtd_plasma_loss_r2(fdtd_plasma *h, int32_t probe, const double *xref_re,
+                        const double *xref_im, double *loss);
+
+/*
+ * dL_b/d(wp2) of that loss after nsteps steps from zero, by the discrete
+ * adjoint: the sub-steps of eqs.(14), (11)+(12), (11) and the ends are
+ * transposed and applied in reverse order, forward states are recomputed
+ * segment by segment from checkpoints taken every ceil(sqrt(nsteps)) steps.
+ * Needs FDTD_FLAG_CHECKPOINT with nsteps <= checkpoint_steps, scheme
+ * CONSISTENT, MUR1 or PEC ends.  If the handle's state is not already a
+ * checkpointed run() of nsteps, that run is done first.  Outputs (host):
+ * loss [batch]; grad [sum(cells)] in grid order (units 1/(rad/s)^2).  The
+ * state (fields, spectra, checkpoints) is left as the forward run made it.
  */
 int fdtd_plasma_grad_r2(fdtd_plasma *h, int64_t nsteps, int32_t probe,
                         const double *xref_re, const double *xref_im,

@@ -58,7 +58,7 @@ class Desc(ctypes.Structure):
         ("cpml_m", ctypes.c_double),
         ("cpml_sigma_max", ctypes.c_double),
         ("steps_per_pass", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("checkpoint_steps", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -84,6 +84,7 @@ def lib():
             "fdtd_plasma_get_fields": [p, i64, p, p, p],
             "fdtd_plasma_steps_done": [p, p],
             "fdtd_plasma_grad_r2": [p, i64, i32, p, p, p, p],
+            "fdtd_plasma_loss_r2": [p, i32, p, p, p],
             "fdtd_plasma_profile": [p, i64, i32, p, p, p, p, p],
             "fdtd_plasma_destroy": [p],
         }

@@ -111,6 +111,19 @@ struct fdtd_plasma {
     std::map<int64_t, hipGraphExec_t> graphs;
     bool poisoned = false;
 
+    // checkpoints (FDTD_FLAG_CHECKPOINT) and adjoint storage
+    int64_t ck_T = 0;          // longest run sized for
+    int64_t ck_s = 0;          // checkpoint interval
+    int64_t ck_n = 0;          // checkpoint slots (steps 0, s, 2s, ...)
+    bool ck_on = false;        // the advance in progress stores checkpoints
+    bool ck_valid = false;     // the state is a checkpointed run() of ck_run steps
+    int64_t ck_run = 0;
+    char *d_ck = nullptr;      // [ck_n][3][state_bytes]
+    char *d_seg = nullptr;     // [ck_s + 1][3][state_bytes]
+    void *d_lam[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    double *d_grad = nullptr, *d_tab = nullptr, *d_gsrc = nullptr, *d_loss = nullptr;
+    double2 *d_xref = nullptr, *d_G = nullptr;
+
     // per-launch timing (fdtd_plasma_profile)
     struct ProfMark {
         const char *name;
@@ -229,6 +242,9 @@ int validate(const fdtd_plasma_desc *d)
         }
         o += n;
     }
+    if ((d->flags & FDTD_FLAG_CHECKPOINT) && (d->checkpoint_steps < 1 || d->checkpoint_steps > (1 << 30)))
+        return fail(FDTD_E_INVALID, "checkpoint_steps %d out of [1, 2^30]", d->checkpoint_steps);
+    if (d->flags & ~FDTD_FLAG_CHECKPOINT) return fail(FDTD_E_INVALID, "unknown flags 0x%x", d->flags);
     if (d->tile_cells != 0 && (d->tile_cells % 256 != 0 || d->tile_cells < 256 || d->tile_cells > 1024))
         return fail(FDTD_E_INVALID, "tile_cells %d: must be 0, 256, 512, 768 or 1024", d->tile_cells);
     if (d->steps_per_pass != 0 && (d->steps_per_pass < 4 || d->steps_per_pass % 4 != 0 ||
@@ -244,6 +260,9 @@ struct Plan {
             o_X = 0, o_Xtmp = 0, o_tw = 0, o_cpml = 0;
     int64_t o_E[2] = {0, 0}, o_H[2] = {0, 0}, o_J[2] = {0, 0}, o_psiE[2] = {0, 0}, o_psiH[2] = {0, 0};
     int64_t o_tiles = 0, o_slots = 0;
+    int64_t o_ck = 0, o_seg = 0, o_lam[2][3] = {{0, 0, 0}, {0, 0, 0}}, o_grad = 0, o_tab = 0,
+            o_gsrc = 0, o_loss = 0, o_xref = 0, o_G = 0;
+    int64_t ck_T = 0, ck_s = 0, ck_n = 0;
     int64_t nodes = 0, state_bytes = 0, psi_bytes = 0;
     int SB = 0;
     std::vector<int64_t> off;
@@ -418,6 +437,22 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         p.o_psiE[i] = L.take(p.psi_bytes);
         p.o_psiH[i] = L.take(p.psi_bytes);
     }
+    p.o_xref = L.take(16 * d->batch * (int64_t)F);
+    p.o_G = L.take(16 * d->batch * (int64_t)F);
+    p.o_loss = L.take(8 * d->batch);
+    if (d->flags & FDTD_FLAG_CHECKPOINT) {
+        p.ck_T = d->checkpoint_steps;
+        p.ck_s = (int64_t)std::ceil(std::sqrt((double)p.ck_T));
+        p.ck_n = p.ck_T / p.ck_s + 1;
+        const int64_t st3 = 3 * round_up(p.state_bytes, kAlign);
+        p.o_ck = L.take(p.ck_n * st3);
+        p.o_seg = L.take((p.ck_s + 1) * st3);
+        for (int i = 0; i < 2; ++i)
+            for (int q = 0; q < 3; ++q) p.o_lam[i][q] = L.take(p.state_bytes);
+        p.o_grad = L.take(8 * p.nodes);
+        p.o_tab = L.take(8 * 11 * p.nodes);
+        p.o_gsrc = L.take(8 * d->batch * p.ck_T);
+    }
     p.o_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.tiles.size()));
     p.o_slots = L.take((int64_t)sizeof(ResidentSlot) * std::max<size_t>(1, p.slots.size()));
     return FDTD_OK;
@@ -477,9 +512,20 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
     const Grids g = h->grids();
     State<T> s = h->state<T>();
     int64_t left = nsteps;
+    const int64_t ck3 = 3 * round_up(h->state_bytes, kAlign);
     while (left > 0) {
         const int slot = (int)(h->steps - h->win_base);
         int64_t room = h->SB - slot;
+        if (h->ck_on) {
+            if (h->steps % h->ck_s == 0 && h->steps / h->ck_s < h->ck_n) {
+                char *dst = h->d_ck + (h->steps / h->ck_s) * ck3;
+                const int64_t sb = round_up(h->state_bytes, kAlign);
+                launch_copy(dst, h->d_E[h->cur], round_up(h->state_bytes, 16), h->stream);
+                launch_copy(dst + sb, h->d_H[h->cur], round_up(h->state_bytes, 16), h->stream);
+                launch_copy(dst + 2 * sb, h->d_J[h->cur], round_up(h->state_bytes, 16), h->stream);
+            }
+            room = std::min<int64_t>(room, h->ck_s - h->steps % h->ck_s);
+        }
         int64_t k;
         static const char *kTiledNames[3] = {"tiled_vacuum", "tiled_plasma", "tiled_cpml"};
         if (h->exec == FDTD_EXEC_STEP) {
@@ -629,6 +675,21 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         h->d_psiE[i] = w + p.o_psiE[i];
         h->d_psiH[i] = w + p.o_psiH[i];
     }
+    h->d_xref = (double2 *)(w + p.o_xref);
+    h->d_G = (double2 *)(w + p.o_G);
+    h->d_loss = (double *)(w + p.o_loss);
+    h->ck_T = p.ck_T;
+    h->ck_s = p.ck_s;
+    h->ck_n = p.ck_n;
+    if (desc->flags & FDTD_FLAG_CHECKPOINT) {
+        h->d_ck = w + p.o_ck;
+        h->d_seg = w + p.o_seg;
+        for (int i = 0; i < 2; ++i)
+            for (int q = 0; q < 3; ++q) h->d_lam[i][q] = w + p.o_lam[i][q];
+        h->d_grad = (double *)(w + p.o_grad);
+        h->d_tab = (double *)(w + p.o_tab);
+        h->d_gsrc = (double *)(w + p.o_gsrc);
+    }
     h->d_tiles = (Tile *)(w + p.o_tiles);
     h->d_slots = (ResidentSlot *)(w + p.o_slots);
 
@@ -681,6 +742,7 @@ int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps)
     int rc = check_handle(h);
     if (rc) return rc;
     if (nsteps < 0) return fail(FDTD_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
+    if (nsteps > 0) h->ck_valid = false;
     return advance(h, nsteps);
 }
 
@@ -689,12 +751,19 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
     int rc = check_handle(h);
     if (rc) return rc;
     if (nsteps < 0) return fail(FDTD_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
+    h->ck_on = h->d_ck != nullptr && nsteps <= h->ck_T;
+    h->ck_valid = false;
     if (h->stream == nullptr) {
         // the legacy null stream cannot be captured: run eagerly
         reset(h);
-        return advance(h, nsteps);
+        rc = advance(h, nsteps);
+        h->ck_valid = h->ck_on && rc == FDTD_OK;
+        h->ck_run = nsteps;
+        h->ck_on = false;
+        return rc;
     }
-    auto it = h->graphs.find(nsteps);
+    const int64_t key = nsteps * 2 + (h->ck_on ? 1 : 0);
+    auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         // capture reset + the whole time loop once for this length
         HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -702,13 +771,13 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
         rc = advance(h, nsteps);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(h->stream, &graph);
-        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (rc) { h->ck_on = false; if (graph) (void)hipGraphDestroy(graph); return rc; }
         if (e != hipSuccess) return fail(FDTD_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
         hipGraphExec_t exec = nullptr;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(FDTD_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-        it = h->graphs.emplace(nsteps, exec).first;
+        it = h->graphs.emplace(key, exec).first;
     } else {
         // bookkeeping identical to what the captured launches did
         h->cur = 0;
@@ -717,7 +786,8 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
         int64_t left = nsteps;
         while (left > 0) {
             const int slot = (int)(h->steps - h->win_base);
-            const int64_t room = h->SB - slot;
+            int64_t room = h->SB - slot;
+            if (h->ck_on) room = std::min<int64_t>(room, h->ck_s - h->steps % h->ck_s);
             int64_t k = h->exec == FDTD_EXEC_STEP ? 1
                         : h->exec == FDTD_EXEC_TILED ? std::min<int64_t>(std::min<int64_t>(left, room), h->Kh)
                                                      : std::min<int64_t>(left, room);
@@ -728,6 +798,9 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
         }
     }
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    h->ck_valid = h->ck_on;
+    h->ck_run = nsteps;
+    h->ck_on = false;
     return FDTD_OK;
 }
 
@@ -788,13 +861,131 @@ int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, d
     return FDTD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Spectra including the partially filled sample window, into h->d_Xtmp.
+void spectra_to_tmp(fdtd_plasma *h)
+{
+    const int64_t rows = h->batch * h->P, nX = rows * h->F;
+    (void)hipMemcpyAsync(h->d_Xtmp, h->d_X, 16 * nX, hipMemcpyDeviceToDevice, h->stream);
+    const int count = (int)(h->steps - h->win_base);
+    launch_dft(h->grids(), h->d_freqs, h->F, h->win_base + 1, count, h->d_tw, h->d_Xtmp, rows,
+               h->stream);
+}
+
+int upload_xref(fdtd_plasma *h, const double *xr, const double *xi)
+{
+    const int64_t nx = h->batch * h->F;
+    std::vector<double2> x(nx);
+    for (int64_t i = 0; i < nx; ++i) {
+        if (!std::isfinite(xr[i]) || !std::isfinite(xi[i]) || (xr[i] == 0.0 && xi[i] == 0.0))
+            return fail(FDTD_E_INVALID, "xref[%lld] must be finite and nonzero", (long long)i);
+        x[i] = make_double2(xr[i], xi[i]);
+    }
+    HIP_TRY(hipMemcpyAsync(h->d_xref, x.data(), 16 * nx, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return FDTD_OK;
+}
+
+// Reverse sweep: per segment, recompute the forward states from its
+// checkpoint into the segment buffer, then transpose the steps in reverse.
+template <typename T>
+int reverse_sweep(fdtd_plasma *h, int64_t Tn, int probe)
+{
+    Grids g = h->grids();
+    Grids gq = g;
+    gq.P = 0;                          // recompute: no probe samples
+    const int64_t sb = round_up(h->state_bytes, kAlign), ck3 = 3 * sb;
+    auto segE = [&](int64_t i) { return (T *)(h->d_seg + i * ck3); };
+    auto segH = [&](int64_t i) { return (T *)(h->d_seg + i * ck3 + sb); };
+    auto segJ = [&](int64_t i) { return (T *)(h->d_seg + i * ck3 + 2 * sb); };
+    for (int i = 0; i < 2; ++i)
+        for (int q = 0; q < 3; ++q) launch_fill(h->d_lam[i][q], round_up(h->state_bytes, 16), h->stream);
+    launch_fill(h->d_grad, round_up(8 * h->nodes, 16), h->stream);
+    int lc = 0;                        // lambda^{m+1} lives in d_lam[lc]
+    const int64_t nseg = (Tn + h->ck_s - 1) / h->ck_s;
+    for (int64_t j = nseg - 1; j >= 0; --j) {
+        const int64_t m0 = j * h->ck_s, m1 = std::min<int64_t>(Tn, m0 + h->ck_s);
+        launch_copy(h->d_seg, h->d_ck + j * ck3, ck3, h->stream);
+        for (int64_t i = 0; i < m1 - m0; ++i) {
+            State<T> s{};
+            s.E[0] = segE(i); s.E[1] = segE(i + 1);
+            s.H[0] = segH(i); s.H[1] = segH(i + 1);
+            s.J[0] = segJ(i); s.J[1] = segJ(i + 1);
+            launch_step<T>(gq, s, 0, h->nodes, m0 + i + 1, 0, h->stream);
+        }
+        for (int64_t m = m1 - 1; m >= m0; --m) {
+            const int64_t i = m - m0;
+            const T *lam[3] = {(const T *)h->d_lam[lc][0], (const T *)h->d_lam[lc][1],
+                               (const T *)h->d_lam[lc][2]};
+            T *out[3] = {(T *)h->d_lam[lc ^ 1][0], (T *)h->d_lam[lc ^ 1][1], (T *)h->d_lam[lc ^ 1][2]};
+            launch_adj_step<T>(g, lam, out, segE(i), segJ(i), segH(i + 1), segE(i + 1), h->d_tab,
+                               h->nodes, h->d_gsrc, Tn, m, probe, h->d_grad, h->stream);
+            lc ^= 1;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FDTD_E_DEVICE, "adjoint launch failed: %s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_plasma_loss_r2(fdtd_plasma *h, int32_t probe, const double *xref_re, const double *xref_im,
+                        double *loss)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!xref_re || !xref_im || !loss) return fail(FDTD_E_INVALID, "output/input pointer is NULL");
+    if (probe < 0 || probe >= h->P) return fail(FDTD_E_INVALID, "probe %d out of range", probe);
+    if (h->steps == 0) return fail(FDTD_E_STATE, "no step taken yet");
+    if ((rc = upload_xref(h, xref_re, xref_im))) return rc;
+    spectra_to_tmp(h);
+    launch_adj_prepare(h->d_Xtmp, h->batch, h->P, h->F, probe, h->d_xref, h->d_G, h->d_loss, h->stream);
+    HIP_TRY(hipMemcpyAsync(loss, h->d_loss, 8 * h->batch, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return FDTD_OK;
+}
+
 int fdtd_plasma_grad_r2(fdtd_plasma *h, int64_t nsteps, int32_t probe, const double *xref_re,
                         const double *xref_im, double *loss, double *grad)
 {
     int rc = check_handle(h);
     if (rc) return rc;
-    (void)nsteps; (void)probe; (void)xref_re; (void)xref_im; (void)loss; (void)grad;
-    return fail(FDTD_E_UNSUPPORTED, "adjoint not built yet");
+    if (!xref_re || !xref_im || !loss || !grad) return fail(FDTD_E_INVALID, "a pointer is NULL");
+    if (!h->d_ck) return fail(FDTD_E_STATE, "created without FDTD_FLAG_CHECKPOINT");
+    if (nsteps < 1 || nsteps > h->ck_T)
+        return fail(FDTD_E_INVALID, "nsteps %lld outside [1, checkpoint_steps=%lld]",
+                    (long long)nsteps, (long long)h->ck_T);
+    if (probe < 0 || probe >= h->P) return fail(FDTD_E_INVALID, "probe %d out of range", probe);
+    if (h->d.scheme != FDTD_SCHEME_CONSISTENT || (h->d.bc != FDTD_BC_MUR1 && h->d.bc != FDTD_BC_PEC))
+        return fail(FDTD_E_UNSUPPORTED, "the adjoint needs the consistent scheme and Mur or PEC ends");
+    if ((rc = upload_xref(h, xref_re, xref_im))) return rc;
+    if (!(h->ck_valid && h->ck_run == nsteps && h->steps == nsteps)) {
+        if ((rc = fdtd_plasma_run(h, nsteps))) return rc;
+    }
+    spectra_to_tmp(h);
+    launch_adj_prepare(h->d_Xtmp, h->batch, h->P, h->F, probe, h->d_xref, h->d_G, h->d_loss, h->stream);
+    launch_adj_source(h->d_freqs, h->F, h->d.dt, h->d_G, h->batch, nsteps, h->d_gsrc, h->stream);
+    launch_adj_coef(h->grids(), h->nodes, h->d_tab, h->stream);
+    rc = h->esize == 8 ? reverse_sweep<double>(h, nsteps, probe) : reverse_sweep<float>(h, nsteps, probe);
+    if (rc) return rc;
+    // the sweep works in the segment buffer: fields, spectra and checkpoints
+    // still hold the forward run, so another loss can reuse it
+    std::vector<double> gpad(h->nodes);
+    HIP_TRY(hipMemcpyAsync(gpad.data(), h->d_grad, 8 * h->nodes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(loss, h->d_loss, 8 * h->batch, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int64_t o = 0;
+    for (int64_t b = 0; b < h->batch; ++b) {
+        std::memcpy(grad + o, gpad.data() + h->off[b], 8 * h->cells[b]);
+        o += h->cells[b];
+    }
+    return FDTD_OK;
 }
 
 int fdtd_plasma_profile(fdtd_plasma *h, int64_t nsteps, int32_t max, char *names, double *ms_total,

@@ -26,7 +26,7 @@ template <typename T, int C, bool PLASMA, bool CPML>
 struct Chunk {
     T E[C], H[C];
     T J[PLASMA ? C : 1];
-    Coef cf[PLASMA ? C : 1];
+    NodeCoef<T> cf[PLASMA ? C : 1];
     uint32_t pmask;                // bit i: node i is plasma
     T pE[CPML ? C : 1], pH[CPML ? C : 1];
     T bE[CPML ? C : 1], aE[CPML ? C : 1], bH[CPML ? C : 1], aH[CPML ? C : 1];
@@ -167,7 +167,7 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (w[i] != 0.0) ck.pmask |= 1u << i;
-            ck.cf[i] = node_coef(w[i], v[i], g.dt, g.dz, g.scheme);
+            ck.cf[i] = node_coef_t<T>(w[i], v[i], g.dt, g.dz, g.scheme);
         }
     }
     if constexpr (CPML) {
@@ -240,8 +240,8 @@ __device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er, T c
         if constexpr (CPML) {
             if (ck.hZone & (1u << i)) {
                 const T dE = er - ck.E[i];
-                ck.pH[i] = __builtin_fma(ck.aH[i], dE, ck.bH[i] * ck.pH[i]);
-                ck.H[i] = __builtin_fma(-ch, dE + ck.pH[i], ck.H[i]);
+                ck.pH[i] = fmat(ck.aH[i], dE, ck.bH[i] * ck.pH[i]);
+                ck.H[i] = fmat(-ch, dE + ck.pH[i], ck.H[i]);
                 continue;
             }
         }
@@ -260,30 +260,39 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T c
         T curl = ck.H[i] - ((i > 0) ? ck.H[i - 1] : Hl);
         if constexpr (CPML) {
             if (ck.eZone & (1u << i)) {
-                ck.pE[i] = __builtin_fma(ck.aE[i], curl, ck.bE[i] * ck.pE[i]);
+                ck.pE[i] = fmat(ck.aE[i], curl, ck.bE[i] * ck.pE[i]);
                 curl = curl + ck.pE[i];
             }
         }
         if constexpr (PLASMA) {
+            // the plasma formula reproduces the vacuum update at vacuum nodes
             Eo[i] = ck.E[i];
-            if (ck.pmask & (1u << i))
-                ck.E[i] = (T)e_update_plasma<T>(ck.E[i], ck.J[i], curl, ck.cf[i]);
-            else
-                ck.E[i] = e_update_vac<T>(ck.E[i], curl, ce);
+            ck.E[i] = e_update_plasma(ck.E[i], ck.J[i], curl, ck.cf[i]);
         } else {
             ck.E[i] = e_update_vac<T>(ck.E[i], curl, ce);
         }
     }
 }
 
+// J update of the chunk; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.
 template <typename T, int C, bool PLASMA, bool CPML>
 __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML> &ck, const T (&Eo)[PLASMA ? C : 1])
 {
     if constexpr (PLASMA) {
 #pragma unroll
-        for (int i = 0; i < C; ++i)
-            if (ck.pmask & (1u << i)) ck.J[i] = (T)j_update<T>(ck.J[i], Eo[i], ck.E[i], ck.cf[i]);
+        for (int i = 0; i < C; ++i) ck.J[i] = j_update<T>(ck.J[i], Eo[i], ck.E[i], ck.cf[i]);
     }
+}
+
+// One time step of a chunk that holds no grid end and no source: H, E, J only.
+template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
+__device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+                                                 GetEr get_er, GetHl get_hl)
+{
+    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
+    T Eo[PLASMA ? C : 1];
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce, Eo);
+    chunk_j<T, C, PLASMA, CPML>(ck, Eo);
 }
 
 // Everything a lane needs to know about the grid ends, source and probes in
@@ -398,11 +407,15 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
     ChunkRole role = chunk_role(g, b, n, k0, tl.lo, tl.hi, C);
     const bool probes = (tl.flags & TILE_PROBE) != 0;
-    for (int st = 0; st < nsteps; ++st) {
-        chunk_step<T, C, PLASMA, CPML>(
-            ck, g, role, m0 + st + 1, [](T e0) { return shfl_down1(e0); },
-            [](T hl) { return shfl_up1(hl); });
-        if (probes) chunk_probes<T, C>(g, b, k0, tl.out_lo, tl.out_hi, ck.E, slot0 + st);
+    auto er = [](T e0) { return shfl_down1(e0); };
+    auto hl = [](T h) { return shfl_up1(h); };
+    if (!(role.left_any || role.right_any || role.src_any || probes)) {
+        for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
+    } else {
+        for (int st = 0; st < nsteps; ++st) {
+            chunk_step<T, C, PLASMA, CPML>(ck, g, role, m0 + st + 1, er, hl);
+            if (probes) chunk_probes<T, C>(g, b, k0, tl.out_lo, tl.out_hi, ck.E, slot0 + st);
+        }
     }
     (void)wave_hi;
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
@@ -502,12 +515,9 @@ void launch_resident(const Grids &g, State<T> &s, int cur, const ResidentSlot *s
                      int waves_per_wg, int C, int nsteps, int64_t m0, int slot0, hipStream_t st)
 {
     (void)C;
-    if (waves_per_wg == 8)
-        hipLaunchKernelGGL((k_resident<T, 8, 8>), dim3((unsigned)nbins), dim3(8 * 64), 0, st, g, s,
-                           cur, slots, nsteps, m0, slot0);
-    else
-        hipLaunchKernelGGL((k_resident<T, 8, 16>), dim3((unsigned)nbins), dim3(16 * 64), 0, st, g, s,
-                           cur, slots, nsteps, m0, slot0);
+    (void)waves_per_wg;   // 8 waves: 512 threads keep the per-node coefficients in VGPRs
+    hipLaunchKernelGGL((k_resident<T, 8, 8>), dim3((unsigned)nbins), dim3(8 * 64), 0, st, g, s,
+                       cur, slots, nsteps, m0, slot0);
 }
 
 template void launch_resident<float>(const Grids &, State<float> &, int, const ResidentSlot *, int64_t,

@@ -100,4 +100,17 @@ void launch_cpml_table(double *tab, int P, double m, double smax, double dt, hip
 
 int resident_max_nodes(int C, int waves);
 
+// ---- adjoint (adjoint1d.hip) -----------------------------------------------
+void launch_adj_coef(const Grids &g, int64_t total, double *tab, hipStream_t st);
+void launch_adj_prepare(const double2 *X, int64_t batch, int P, int F, int probe,
+                        const double2 *xref, double2 *G, double *loss, hipStream_t st);
+void launch_adj_source(const double *freqs, int F, double dt, const double2 *G, int64_t batch,
+                       int64_t T, double *gsrc, hipStream_t st);
+template <typename T>
+void launch_adj_step(const Grids &g, const T *const lam[3], T *const out[3], const T *En,
+                     const T *Jn, const T *Hh, const T *En1, const double *tab, int64_t total,
+                     const double *gsrc, int64_t T_, int64_t m, int probe, double *grad,
+                     hipStream_t st);
+void launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
+
 }  // namespace fdtdp

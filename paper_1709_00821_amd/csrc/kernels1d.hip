@@ -66,9 +66,9 @@ __global__ void k_step_h(Grids g, State<T> s, int cur, int64_t total)
         if (slot >= 0) {
             const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
             const T bH = (T)g.cpml[2 * g.cpmlP + tab], aH = (T)g.cpml[3 * g.cpmlP + tab];
-            const T psi = __builtin_fma(aH, dE, bH * s.psiH[cur][ps]);
+            const T psi = fmat(aH, dE, bH * s.psiH[cur][ps]);
             s.psiH[nxt][ps] = psi;
-            Hn = __builtin_fma(-(T)g.ch, dE + psi, s.H[cur][off + k]);
+            Hn = fmat(-(T)g.ch, dE + psi, s.H[cur][off + k]);
         } else {
             Hn = h_update<T>(s.H[cur][off + k], E[k], E[k + 1], (T)g.ch);
         }
@@ -94,7 +94,7 @@ __device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, in
         if (slot >= 0) {
             const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
             const T bE = (T)g.cpml[tab], aE = (T)g.cpml[g.cpmlP + tab];
-            const T psi = __builtin_fma(aE, curl, bE * s.psiE[cur][ps]);
+            const T psi = fmat(aE, curl, bE * s.psiE[cur][ps]);
             if (write) s.psiE[nxt][ps] = psi;
             curl = curl + psi;
         }
@@ -102,17 +102,17 @@ __device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, in
     const T Eo = s.E[cur][off + k];
     const double wp2 = g.wp2[off + k];
     T En;
-    Coef c;
+    NodeCoef<T> c;
     if (wp2 != 0.0) {
-        c = node_coef(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
-        En = (T)e_update_plasma<T>(Eo, s.J[cur][off + k], curl, c);
+        c = node_coef_t<T>(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
+        En = e_update_plasma(Eo, s.J[cur][off + k], curl, c);
     } else {
         En = e_update_vac<T>(Eo, curl, (T)g.ce);
     }
     if (k == g.src[b])
         En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
     if (write) {
-        s.J[nxt][off + k] = (wp2 != 0.0) ? (T)j_update<T>(s.J[cur][off + k], Eo, En, c) : (T)0;
+        s.J[nxt][off + k] = (wp2 != 0.0) ? j_update<T>(s.J[cur][off + k], Eo, En, c) : (T)0;
     }
     return En;
 }
@@ -192,8 +192,8 @@ __global__ __launch_bounds__(256) void k_dft_accum(const double *samp, int SB, i
     for (int i = lane; i < count; i += 64) {
         const double v = sp[i];
         const double2 w = tw[(int64_t)i * F + f];
-        ar = __builtin_fma(v, w.x, ar);
-        ai = __builtin_fma(v, w.y, ai);
+        ar = fmat(v, w.x, ar);
+        ai = fmat(v, w.y, ai);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {

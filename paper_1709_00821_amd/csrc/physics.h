@@ -31,6 +31,7 @@ __host__ __device__ inline double mu0() { return 1.0 / (kEps0 * kC0 * kC0); }
 
 struct Coef {
     double CA, CJ, CH, a, b1, b2;
+    double CAm1;   // CA - 1, formed directly (no cancellation); +0 in vacuum
 };
 
 // phi-functions of the exponential integrator.  For x <= 0.5 the closed forms
@@ -84,6 +85,7 @@ __host__ __device__ inline Coef node_coef(double wp2, double nu, double dt, doub
     if (scheme == 2) {  // ETD1, eq.(9)
         c.b1 = kEps0 * wp2 * dt * p1;
         c.b2 = 0.0;
+        c.CAm1 = 0.0 - 0.5 * w * p1;
         c.CA = 1.0 - 0.5 * w * p1;
         c.CJ = dt * (1.0 + a) / (2.0 * kEps0);
         c.CH = dt / (kEps0 * dz);
@@ -92,6 +94,7 @@ __host__ __device__ inline Coef node_coef(double wp2, double nu, double dt, doub
     c.b1 = kEps0 * wp2 * dt * (p1 - p2);
     c.b2 = kEps0 * wp2 * dt * p2;
     const double D = 1.0 + 0.5 * w * p2;
+    c.CAm1 = 0.0 - 0.5 * w * p1 / D;
     c.CA = 1.0 - 0.5 * w * p1 / D;
     if (scheme == 1) {  // eq.(13) as printed
         c.CJ = dt * (1.0 + a) / (2.0 * kEps0);
@@ -156,6 +159,17 @@ __host__ __device__ inline void cpml_ab(double depth, int P, double m, double sm
 
 // ---- per-node updates (storage type T; plasma nodes computed in FP64) ----
 
+// Fused multiply-add in the precision of T (__builtin_fma alone would promote
+// float operands to double).
+__host__ __device__ __forceinline__ float fmat(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+__host__ __device__ __forceinline__ double fmat(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+
 // Soft source: E + s, rounded once to the storage type.
 template <typename T>
 __device__ __forceinline__ T add_source(T E, double s)
@@ -166,29 +180,62 @@ __device__ __forceinline__ T add_source(T E, double s)
 template <typename T>
 __device__ __forceinline__ T h_update(T H, T Eleft, T Eright, T ch)
 {
-    return __builtin_fma(-ch, Eright - Eleft, H);
+    return fmat(-ch, Eright - Eleft, H);
 }
 
 // Vacuum node: CA = 1, J = 0, CH = dt/(eps0 dz).
 template <typename T>
 __device__ __forceinline__ T e_update_vac(T E, T curl, T ce)
 {
-    return __builtin_fma(-ce, curl, E);
+    return fmat(-ce, curl, E);
 }
 
-// Plasma node: E_new = CA E - CJ J - CH curl, in FP64 whatever T is.
+// Coefficients as the kernels hold them: the E-update triple in the storage
+// precision (FP64: CA, CJ, CH; FP32: CA-1, CJ, CH, each rounded once from
+// FP64), the exponential-integrator triple of the J update always in FP64.
 template <typename T>
-__device__ __forceinline__ double e_update_plasma(T E, T J, T curl, const Coef &c)
+struct NodeCoef {
+    T eA, eJ, eH;
+    double a, b1, b2;
+};
+
+template <typename T>
+__host__ __device__ inline NodeCoef<T> node_coef_t(double wp2, double nu, double dt, double dz,
+                                                   int scheme)
 {
-    const double e = (double)E, j = (double)J, cu = (double)curl;
-    return __builtin_fma(-c.CH, cu, __builtin_fma(-c.CJ, j, c.CA * e));
+    const Coef c = node_coef(wp2, nu, dt, dz, scheme);
+    NodeCoef<T> r;
+    r.eA = sizeof(T) == 8 ? (T)c.CA : (T)c.CAm1;
+    r.eJ = (T)c.CJ;
+    r.eH = (T)c.CH;
+    r.a = c.a;
+    r.b1 = c.b1;
+    r.b2 = c.b2;
+    return r;
 }
 
-// J_new = a J + b1 E_old + b2 E_new (FP64).
-template <typename T>
-__device__ __forceinline__ double j_update(T J, T Eold, T Enew, const Coef &c)
+// Plasma node E update.  FP64: CA E - CJ J - CH curl.  FP32: the same in
+// delta form, E + (CA-1) E - CJ J - CH curl, so that CA = 1 - 2.5e-4 is not
+// rounded to FP32 (which would perturb the plasma term by ~2e-4).  At a vacuum
+// node (CA-1 = +0, CA = 1, J = +0, CH = dt/(eps0 dz)) both forms give exactly
+// the bits of e_update_vac, signed zeros included.
+__device__ __forceinline__ double e_update_plasma(double E, double J, double curl,
+                                                  const NodeCoef<double> &c)
 {
-    return __builtin_fma(c.b2, (double)Enew, __builtin_fma(c.b1, (double)Eold, c.a * (double)J));
+    return fmat(-c.eH, curl, fmat(-c.eJ, J, c.eA * E));
+}
+__device__ __forceinline__ float e_update_plasma(float E, float J, float curl,
+                                                 const NodeCoef<float> &c)
+{
+    return fmat(-c.eH, curl, fmat(-c.eJ, J, fmat(c.eA, E, E)));
+}
+
+// J_new = a J + b1 E_old + b2 E_new, in FP64 for both storage precisions
+// (eq.(11): the exp(-nu dt) fractions keep their FP64 accuracy).
+template <typename T>
+__device__ __forceinline__ T j_update(T J, T Eold, T Enew, const NodeCoef<T> &c)
+{
+    return (T)__builtin_fma(c.b2, (double)Enew, __builtin_fma(c.b1, (double)Eold, c.a * (double)J));
 }
 
 }  // namespace fdtdp

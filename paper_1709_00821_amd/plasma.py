@@ -21,7 +21,7 @@ def _as_list(problems) -> List[Problem1D]:
 
 
 def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: int = 0,
-              steps_per_pass: int = 0, checkpoint: bool = False, stream_handle: int = 0):
+              steps_per_pass: int = 0, checkpoint: int = 0, stream_handle: int = 0):
     """Build the C descriptor; returns (desc, arrays it points into)."""
     probs = _as_list(problems)
     p0 = probs[0]
@@ -48,6 +48,7 @@ def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: 
     d.bc = L.BC[p0.bc]
     d.exec = L.EXEC[exec]
     d.flags = L.FLAG_CHECKPOINT if checkpoint else 0
+    d.checkpoint_steps = int(checkpoint) if checkpoint else 0
     d.batch = len(probs)
     d.cells = cells.ctypes.data
     d.dz, d.dt = p0.dz, p0.dt
@@ -76,7 +77,7 @@ class FdtdPlasma:
 
     def __init__(self, problems: Union[Problem1D, Sequence[Problem1D]], precision: str = "f64",
                  exec: str = "auto", tile_cells: int = 0, steps_per_pass: int = 0,
-                 checkpoint: bool = False, stream: Optional[torch.cuda.Stream] = None,
+                 checkpoint: int = 0, stream: Optional[torch.cuda.Stream] = None,
                  device: Union[int, str, torch.device] = "cuda"):
         probs = _as_list(problems)
         self.problems = probs
@@ -128,6 +129,28 @@ class FdtdPlasma:
         L.check(L.lib().fdtd_plasma_get_fields(self.h, grid, E.ctypes.data, H.ctypes.data,
                                                J.ctypes.data))
         return {"E": E, "H": H, "J": J}
+
+    def loss_r2(self, xref: np.ndarray, probe: int = 0) -> np.ndarray:
+        """L_b = sum_f |(X_b - xref_b)/xref_b|^2 at `probe`, per grid; xref [batch, F]."""
+        B, F = len(self.problems), self.desc.n_freqs
+        xr = np.ascontiguousarray(np.real(xref).reshape(B, F), np.float64)
+        xi = np.ascontiguousarray(np.imag(xref).reshape(B, F), np.float64)
+        loss = np.zeros(B)
+        L.check(L.lib().fdtd_plasma_loss_r2(self.h, probe, xr.ctypes.data, xi.ctypes.data,
+                                            loss.ctypes.data))
+        return loss
+
+    def grad_r2(self, nsteps: int, xref: np.ndarray, probe: int = 0):
+        """(loss [batch], dL/d wp2 [sum cells]) by the discrete adjoint with
+        sqrt(T) checkpoints (needs checkpoint >= nsteps at construction)."""
+        B, F = len(self.problems), self.desc.n_freqs
+        xr = np.ascontiguousarray(np.real(xref).reshape(B, F), np.float64)
+        xi = np.ascontiguousarray(np.imag(xref).reshape(B, F), np.float64)
+        loss = np.zeros(B)
+        grad = np.zeros(int(self.cells.sum()))
+        L.check(L.lib().fdtd_plasma_grad_r2(self.h, int(nsteps), probe, xr.ctypes.data,
+                                            xi.ctypes.data, loss.ctypes.data, grad.ctypes.data))
+        return loss, grad
 
     def profile(self, nsteps: int) -> dict:
         """Advance nsteps eagerly with HIP events around every launch on the

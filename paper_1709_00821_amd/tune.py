@@ -34,3 +34,65 @@ def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0) -
     if steps_per_pass:
         out["steps_per_pass"] = steps_per_pass
     return out
+
+
+def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
+          tiles=(256, 512, 768, 1024), depths=(8, 12, 16, 24, 32, 48, 64), log=print):
+    """Time run(steps) on a plasma/vacuum grid of n cells for every launch
+    shape; returns [(tile_cells, steps_per_pass, Mcell-updates/s)]."""
+    import torch
+    from . import workloads as W
+    from .plasma import FdtdPlasma
+    p = W.large_c2(n=n, steps=steps)
+    out = []
+    for tc in tiles:
+        for k in depths:
+            if tc <= 2 * k + 64:
+                continue
+            h = FdtdPlasma(p, precision=precision, exec="tiled", tile_cells=tc, steps_per_pass=k)
+            h.run(steps)
+            h.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(h.stream)
+            for _ in range(reps):
+                h.run(steps)
+            e1.record(h.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            h.close()
+            rate = n * steps / (ms / 1e3) / 1e6
+            out.append((tc, k, rate))
+            log(f"tune {precision} tile_cells={tc:5d} steps_per_pass={k:3d}: {ms:8.3f} ms "
+                f"{rate:10.0f} Mcell/s")
+    return out
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="sweep launch shapes and record the best")
+    ap.add_argument("--precision", nargs="+", default=["f32", "f64"])
+    ap.add_argument("--cells", type=int, default=1 << 22)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args(argv)
+    table = {}
+    if os.path.exists(args.out):
+        try:
+            table = json.load(open(args.out))
+        except ValueError:
+            table = {}
+    g = table.setdefault("gfx950", {})
+    for prec in args.precision:
+        res = sweep(prec, n=args.cells, steps=args.steps, log=lambda m: print(m, flush=True))
+        tc, k, rate = max(res, key=lambda r: r[2])
+        g.setdefault(prec, {})["large"] = {"tile_cells": tc, "steps_per_pass": k,
+                                          "mcells": round(rate, 1), "cells": args.cells,
+                                          "steps": args.steps}
+        g[prec]["sweep"] = [[a, b, round(c, 1)] for a, b, c in res]
+        print(f"best {prec}: tile_cells={tc} steps_per_pass={k} {rate:.0f} Mcell/s", flush=True)
+    json.dump(table, open(args.out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+"""GPU adjoint: dL/d(wp2) of L = sum_f |R(f)|^2 by the library's discrete
+adjoint (sqrt(T) checkpoints) against the FP64 oracle's full-trajectory
+adjoint and against FP64 central finite differences."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_00821_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_00821_amd import plasma
+    return plasma
+
+
+def small_problem(seed=3, n=300, bc="mur"):
+    rng = np.random.default_rng(seed)
+    p = W.random_slab(rng, n, n_freqs=8, bc=bc)
+    return p.copy(probes=np.array([10, n - 20]), src_cell=30)
+
+
+@pytest.mark.parametrize("bc,T", [("mur", 800), ("pec", 700), ("mur", 1)])
+def test_fp64_adjoint_matches_oracle(G, bc, T):
+    p = small_problem(bc=bc)
+    say(f"case adjoint fp64 bc={bc} n={p.n} steps={T}")
+    xv = oracle.run(p.vacuum(), T)["X"][0]
+    Lo, go, Xo = oracle.adjoint_r2(p, T, xv)
+    with G.FdtdPlasma(p, precision="f64", exec="tiled", checkpoint=T) as h:
+        L, g = h.grad_r2(T, xv.reshape(1, -1))
+    assert abs(L[0] - Lo) <= 1e-12 * abs(Lo)
+    assert np.max(np.abs(g - go)) <= 1e-10 * np.max(np.abs(go))
+
+
+def test_batched_adjoint_and_loss(G):
+    rng = np.random.default_rng(9)
+    probs = [W.random_slab(rng, n, n_freqs=6) for n in (150, 420, 900)]
+    probs = [q.copy(freqs=probs[0].freqs, probes=np.array([5, q.n - 6])) for q in probs]
+    T = 600
+    say(f"case batched adjoint lens={[q.n for q in probs]} steps={T}")
+    xrefs = np.stack([oracle.run(q.vacuum(), T)["X"][0] for q in probs])
+    with G.FdtdPlasma(probs, precision="f64", exec="resident", checkpoint=T) as h:
+        h.run(T)
+        L1 = h.loss_r2(xrefs)
+        L, g = h.grad_r2(T, xrefs)
+        L2, g2 = h.grad_r2(T, xrefs)         # reuses the checkpoints
+    assert np.array_equal(L, L1) and np.array_equal(g, g2)
+    o = 0
+    for b, q in enumerate(probs):
+        Lo, go, _ = oracle.adjoint_r2(q, T, xrefs[b])
+        assert abs(L[b] - Lo) <= 1e-12 * abs(Lo)
+        gb = g[o:o + q.n]
+        assert np.max(np.abs(gb - go)) <= 1e-10 * np.max(np.abs(go)), b
+        o += q.n
+
+
+def test_autograd_matches_grad(G):
+    import torch
+    from paper_1709_00821_amd.autograd import reflection_loss
+    p = small_problem(seed=5, n=200)
+    T = 400
+    say("case autograd RLoss")
+    xv = oracle.run(p.vacuum(), T)["X"][0]
+    w = torch.tensor(p.wp2, dtype=torch.float64, requires_grad=True)
+    L = reflection_loss(w, p, xv, T, precision="f64")
+    L.backward(torch.tensor(2.0, dtype=torch.float64))
+    Lo, go, _ = oracle.adjoint_r2(p, T, xv)
+    assert abs(L.item() - Lo) <= 1e-12 * Lo
+    assert np.max(np.abs(w.grad.numpy() - 2 * go)) <= 1e-10 * np.max(np.abs(2 * go))
+
+
+def fd_gradients(G, p, T, xv, cells, dirs, hrel=1e-3):
+    """FP64 central differences, all perturbed grids in one batched launch."""
+    h_abs = hrel * np.max(p.wp2)
+    probs = []
+    for k in cells:
+        for s in (+1, -1):
+            w = p.wp2.copy()
+            hk = hrel * w[k] if w[k] > 0 else h_abs
+            w[k] += s * hk
+            probs.append(p.copy(wp2=w))
+    for v in dirs:
+        for s in (+1, -1):
+            probs.append(p.copy(wp2=p.wp2 + s * h_abs * v))
+    with G.FdtdPlasma(probs, precision="f64", exec="tiled") as hh:
+        hh.run(T)
+        Lb = hh.loss_r2(np.tile(xv, (len(probs), 1)))
+    out = []
+    for i, k in enumerate(cells):
+        hk = hrel * p.wp2[k] if p.wp2[k] > 0 else h_abs
+        out.append((Lb[2 * i] - Lb[2 * i + 1]) / (2 * hk))
+    base = 2 * len(cells)
+    dd = [(Lb[base + 2 * j] - Lb[base + 2 * j + 1]) / (2 * h_abs) for j in range(len(dirs))]
+    return np.array(out), np.array(dd)
+
+
+def test_c5_fp32_adjoint_vs_fd_and_oracle(G):
+    """The 8000-cell, 20000-step gradient: FP32 forward + adjoint against FP64
+    central differences (h = 1e-3 relative) on 64 seeded cells and 4 random
+    directions, and against the FP64 oracle adjoint (full trajectory)."""
+    p = W.adjoint_c5()
+    T = p.steps
+    rng = np.random.default_rng(1712)
+    cells = np.sort(rng.choice(np.arange(3000, 5000), 64, replace=False))
+    dirs = [rng.normal(size=p.n) * (p.wp2 > 0) for _ in range(4)]
+    say(f"case c5 adjoint fp32 n={p.n} steps={T}: vacuum reference")
+    with G.FdtdPlasma(p.vacuum(), precision="f64", exec="tiled") as hv:
+        hv.run(T)
+        xv = hv.spectra()[0, 0]
+    say("case c5: fp32 forward + adjoint")
+    with G.FdtdPlasma(p, precision="f32", exec="tiled", checkpoint=T) as h:
+        L32, g32 = h.grad_r2(T, xv.reshape(1, -1))
+    say("case c5: fp64 finite differences (batched)")
+    fd, fdd = fd_gradients(G, p, T, xv, cells, dirs)
+    rel = np.linalg.norm(g32[cells] - fd) / np.linalg.norm(fd)
+    say(f"c5 fp32 adjoint vs fp64 FD: rel {rel:.2e}")
+    assert rel <= 1e-4
+    big = np.abs(fd) >= 1e-2 * np.max(np.abs(fd))
+    assert np.all(np.abs(g32[cells][big] - fd[big]) <= 1e-4 * np.abs(fd[big]) + 1e-4 * np.max(np.abs(fd)))
+    proj = np.array([g32 @ v for v in dirs])
+    assert np.max(np.abs(proj - fdd) / np.abs(fdd)) <= 1e-4
+    say("case c5: fp64 oracle adjoint (full trajectory)")
+    Lo, go, _ = oracle.adjoint_r2(p, T, xv)
+    relo = np.linalg.norm(g32 - go) / np.linalg.norm(go)
+    say(f"c5 fp32 adjoint vs fp64 oracle adjoint: rel {relo:.2e}; loss {L32[0]:.6e} vs {Lo:.6e}")
+    assert relo <= 1e-4
