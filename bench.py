@@ -83,6 +83,111 @@ def roofline(prof, precision):
             "launches": calls}
 
 
+# Algorithmic floating-point operations per node-update (eqs.(14), (12)+(11)
+# solved, (11)): H: subtract + FMA = 3; vacuum E: 3; plasma E: subtract,
+# multiply, two FMAs = 6; J: multiply + two FMAs = 5.
+FLOPS_VAC = 6
+FLOPS_PLASMA = 14
+# MI355X vector peak without packed FP32 (disabled in this build): 256 CUs x
+# 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s, FP32 and FP64.
+VALU_PEAK_TFLOPS = 78.6
+
+
+def alu_roofline(prof, kernel, steps_per_launch):
+    """The tiled kernels do K steps per launch on data held in VGPRs; their
+    ceiling is VALU issue: achieved = algorithmic flops of the node-updates a
+    launch delivers / mean launch time."""
+    ms_tot, calls, units = prof[kernel]
+    per = FLOPS_PLASMA if kernel in ("tiled_plasma", "tiled_cpml") else FLOPS_VAC
+    flops = per * units / calls * steps_per_launch
+    avg_s = ms_tot / calls / 1e3
+    ach = flops / avg_s / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": round(ach, 2), "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": None,
+            "flops_per_launch": int(flops), "avg_launch_us": round(avg_s * 1e6, 2), "launches": calls}
+
+
+def batched_leg(precision="f32", n_slabs=4096, T=8000, reps=2):
+    """4096 independent slabs of uneven length in one handle."""
+    import torch
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd import tune as TU
+    from paper_1709_00821_amd.plasma import FdtdPlasma
+    slabs = W.batch_c4(n_slabs=n_slabs, steps=T)
+    cells = sum(q.n for q in slabs)
+    tune = TU.pick(precision, cells)
+    h = FdtdPlasma(slabs, precision=precision, exec="auto", **tune)
+    h.run(T)
+    h.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    for _ in range(reps):
+        h.run(T)
+    e1.record(h.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    h.close()
+    log(f"bench: batched {n_slabs} slabs ({cells} nodes) x {T} steps: {ms:.2f} ms")
+    return {"value": round(cells * T / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+            "ms": round(ms, 3), "slabs": n_slabs, "nodes": cells, "time_steps": T,
+            "precision": precision, "exec": "tiled over the concatenated slabs",
+            "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"]}
+
+
+def adjoint_leg(precision="f32"):
+    """Gradient of sum_f |R|^2 w.r.t. wp2 per node: 8000 nodes, 20000 steps,
+    forward with sqrt(T) checkpoints + reverse sweep with recompute."""
+    import torch
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd.plasma import FdtdPlasma
+    p = W.adjoint_c5()
+    T = p.steps
+    with FdtdPlasma(p.vacuum(), precision="f64", exec="tiled") as hv:
+        hv.run(T)
+        xv = hv.spectra()[0, 0].reshape(1, -1)
+    h = FdtdPlasma(p, precision=precision, exec="tiled", checkpoint=T)
+    h.run(T)
+    h.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(h.stream)
+    h.run(T)
+    e1.record(h.stream)
+    L, g = h.grad_r2(T, xv)          # reuses the checkpointed forward run
+    e2.record(h.stream)
+    e2.synchronize()
+    fwd_ms, adj_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    h.close()
+    tot = fwd_ms + adj_ms
+    log(f"bench: adjoint {p.n} nodes x {T} steps: forward {fwd_ms:.2f} ms, reverse {adj_ms:.2f} ms")
+    return {"value": round(p.n * T / (tot / 1e3) / 1e6, 1), "unit": "forward-equivalent Mcell/s",
+            "forward_ms": round(fwd_ms, 3), "reverse_ms": round(adj_ms, 3),
+            "nodes": p.n, "time_steps": T, "precision": precision,
+            "checkpoint_interval": int(math.ceil(math.sqrt(T)))}
+
+
+def c1_leg(reps=5):
+    """The 1000-cell slab (latency bound: the state fits one CU)."""
+    import torch
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd.plasma import FdtdPlasma
+    p = W.slab_c1()
+    T = p.steps
+    h = FdtdPlasma(p, precision="f64", exec="resident")
+    h.run(T)
+    h.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    for _ in range(reps):
+        h.run(T)
+    e1.record(h.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    h.close()
+    return {"value": round(p.n * T / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+            "ms": round(ms, 3), "nodes": p.n, "time_steps": T, "precision": "f64",
+            "exec": "resident (one workgroup)"}
+
+
 def cpu_baseline(p, steps):
     import oracle
     log(f"bench: cpu baseline: oracle on the full {p.n}-cell grid for {steps} steps")
@@ -121,6 +226,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the batched, adjoint and C1 legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -131,6 +239,20 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        # one plain device-to-device blit of known size (the HIP runtime's copy
+        # kernel), for scaling the hardware byte counters
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        nbytes = 1 << 30
+        x = torch.full((nbytes // 4,), 1.0, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        rc = hip.hipMemcpy(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                           ctypes.c_size_t(nbytes), 3)          # hipMemcpyDeviceToDevice
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration: hipMemcpy of {nbytes} bytes (rc {rc})")
+        del x, y
     from paper_1709_00821_amd import workloads as W
     from paper_1709_00821_amd import tune as TU
 
@@ -147,7 +269,8 @@ def main():
     ms, X, prof, tune = results[args.precision]
     cells = p.n
     value = cells * T / (ms / 1e3) / 1e6
-    rl = roofline(prof, args.precision)
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    rl = alu_roofline(prof, dom, tune["steps_per_pass"])
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -159,6 +282,7 @@ def main():
                    "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"],
                    "fields": args.precision, "coefficients_dft": "f64"},
         "roofline": rl,
+        "hbm_view": roofline(prof, args.precision),
         "single_step_bound_mcells": round(HBM_PEAK_GBS * 1e9 / (
             0.5 * algorithmic_bytes_per_node(args.precision, True)
             + 0.5 * algorithmic_bytes_per_node(args.precision, False)) / 1e6, 1),
@@ -168,9 +292,17 @@ def main():
     for prec, (ms2, X2, prof2, tune2) in results.items():
         if prec == args.precision:
             continue
+        dom2 = max(prof2.items(), key=lambda kv: kv[1][0])[0]
         out[prec] = {"value": round(cells * T / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(ms2, 3),
-                     "roofline": roofline(prof2, prec),
+                     "roofline": alu_roofline(prof2, dom2, tune2["steps_per_pass"]),
+                     "hbm_view": roofline(prof2, prec),
                      "tile_cells": tune2["tile_cells"], "steps_per_pass": tune2["steps_per_pass"]}
+    if not args.no_legs:
+        out["batched"] = batched_leg()
+        out["batched"]["vs_plain"] = round(out["batched"]["value"] / out["value"], 3)
+        out["adjoint"] = adjoint_leg()
+        out["adjoint"]["vs_plain"] = round(out["adjoint"]["value"] / out["value"], 4)
+        out["c1_latency"] = c1_leg()
     if not args.no_check:
         log("bench: oracle spectra on the source's light cone (exact)")
         t0 = time.perf_counter()

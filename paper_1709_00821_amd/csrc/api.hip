@@ -111,6 +111,11 @@ struct fdtd_plasma {
     std::map<int64_t, hipGraphExec_t> graphs;
     bool poisoned = false;
 
+    // side stream for the few CPML-touching tiles, which otherwise add their
+    // serial latency to every pass; fork/join through events (capturable)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
     // checkpoints (FDTD_FLAG_CHECKPOINT) and adjoint storage
     int64_t ck_T = 0;          // longest run sized for
     int64_t ck_s = 0;          // checkpoint interval
@@ -535,13 +540,24 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
             prof_end(h);
         } else if (h->exec == FDTD_EXEC_TILED) {
             k = std::min<int64_t>(std::min<int64_t>(left, room), h->Kh);
+            // the CPML class (a handful of tiles at the grid ends) runs beside
+            // the bulk classes: all classes of a pass write disjoint nodes
+            const bool fork = h->side && h->ntiles[2] && !h->profiling;
+            if (fork) {
+                (void)hipEventRecord(h->ev_fork, h->stream);
+                (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+                launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[2], h->ntiles[2], 2,
+                                h->tileC, (int)k, h->steps, slot, h->side);
+                (void)hipEventRecord(h->ev_join, h->side);
+            }
             for (int c = 0; c < 3; ++c)
-                if (h->ntiles[c]) {
+                if (h->ntiles[c] && !(fork && c == 2)) {
                     prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                     launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c,
                                     h->tileC, (int)k, h->steps, slot, h->stream);
                     prof_end(h);
                 }
+            if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
         } else {
             k = std::min<int64_t>(left, room);
             prof_begin(h, "resident", h->real_nodes);
@@ -639,6 +655,9 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     h->d.freqs_hz = nullptr;
 
     auto undo = [&](int code) {
+        if (h->side) (void)hipStreamDestroy(h->side);
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->ev_join) (void)hipEventDestroy(h->ev_join);
         if (h->owns_ws && h->ws) (void)hipFree(h->ws);
         delete h;
         return code;
@@ -727,6 +746,13 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         const double smax = desc->cpml_sigma_max > 0 ? desc->cpml_sigma_max
                                                      : 0.8 * (m + 1.0) / (eta0 * desc->dz);
         launch_cpml_table(h->d_cpml, desc->cpml_cells, m, smax, desc->dt, st);
+    }
+    if (h->exec == FDTD_EXEC_TILED && h->ntiles[2] > 0 && h->stream != nullptr) {
+        // default priority (no priority streams), non-blocking w.r.t. the null stream
+        if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+            return undo(fail(FDTD_E_DEVICE, "side stream creation failed"));
     }
     reset(h);
     // the host staging vectors die with this scope: wait for the copies
@@ -1035,6 +1061,12 @@ int fdtd_plasma_destroy(fdtd_plasma *h)
 {
     if (!h) return FDTD_OK;
     (void)hipStreamSynchronize(h->stream);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
     delete h;

@@ -31,7 +31,7 @@ def small_problem(seed=3, n=300, bc="mur"):
     return p.copy(probes=np.array([10, n - 20]), src_cell=30)
 
 
-@pytest.mark.parametrize("bc,T", [("mur", 800), ("pec", 700), ("mur", 1)])
+@pytest.mark.parametrize("bc,T", [("mur", 800), ("pec", 700), ("mur", 150)])
 def test_fp64_adjoint_matches_oracle(G, bc, T):
     p = small_problem(bc=bc)
     say(f"case adjoint fp64 bc={bc} n={p.n} steps={T}")
@@ -46,7 +46,8 @@ def test_fp64_adjoint_matches_oracle(G, bc, T):
 def test_batched_adjoint_and_loss(G):
     rng = np.random.default_rng(9)
     probs = [W.random_slab(rng, n, n_freqs=6) for n in (150, 420, 900)]
-    probs = [q.copy(freqs=probs[0].freqs, probes=np.array([5, q.n - 6])) for q in probs]
+    # probes 25 nodes from the source so that every reference spectrum is nonzero
+    probs = [q.copy(freqs=probs[0].freqs, probes=np.array([5, q.n - 6]), src_cell=30) for q in probs]
     T = 600
     say(f"case batched adjoint lens={[q.n for q in probs]} steps={T}")
     xrefs = np.stack([oracle.run(q.vacuum(), T)["X"][0] for q in probs])
@@ -58,8 +59,12 @@ def test_batched_adjoint_and_loss(G):
     assert np.array_equal(L, L1) and np.array_equal(g, g2)
     o = 0
     for b, q in enumerate(probs):
-        Lo, go, _ = oracle.adjoint_r2(q, T, xrefs[b])
-        assert abs(L[b] - Lo) <= 1e-12 * abs(Lo)
+        Lo, go, Xo = oracle.adjoint_r2(q, T, xrefs[b])
+        # R = (X - Xref)/Xref cancels when |R| is small: the spectra's 1e-14
+        # relative error enters L through 2 |R| |X/Xref|, not through L itself
+        R = (Xo - xrefs[b]) / xrefs[b]
+        cond = np.sum(2 * np.abs(R) * np.abs(Xo / xrefs[b]))
+        assert abs(L[b] - Lo) <= 1e-12 * (abs(Lo) + cond), b
         gb = g[o:o + q.n]
         assert np.max(np.abs(gb - go)) <= 1e-10 * np.max(np.abs(go)), b
         o += q.n
@@ -90,9 +95,9 @@ def fd_gradients(G, p, T, xv, cells, dirs, hrel=1e-3):
             hk = hrel * w[k] if w[k] > 0 else h_abs
             w[k] += s * hk
             probs.append(p.copy(wp2=w))
-    for v in dirs:
+    for v in dirs:                      # relative perturbation hrel * v_k * wp2_k
         for s in (+1, -1):
-            probs.append(p.copy(wp2=p.wp2 + s * h_abs * v))
+            probs.append(p.copy(wp2=p.wp2 * (1 + s * hrel * v)))
     with G.FdtdPlasma(probs, precision="f64", exec="tiled") as hh:
         hh.run(T)
         Lb = hh.loss_r2(np.tile(xv, (len(probs), 1)))
@@ -101,7 +106,7 @@ def fd_gradients(G, p, T, xv, cells, dirs, hrel=1e-3):
         hk = hrel * p.wp2[k] if p.wp2[k] > 0 else h_abs
         out.append((Lb[2 * i] - Lb[2 * i + 1]) / (2 * hk))
     base = 2 * len(cells)
-    dd = [(Lb[base + 2 * j] - Lb[base + 2 * j + 1]) / (2 * h_abs) for j in range(len(dirs))]
+    dd = [(Lb[base + 2 * j] - Lb[base + 2 * j + 1]) / (2 * hrel) for j in range(len(dirs))]
     return np.array(out), np.array(dd)
 
 
@@ -113,7 +118,7 @@ def test_c5_fp32_adjoint_vs_fd_and_oracle(G):
     T = p.steps
     rng = np.random.default_rng(1712)
     cells = np.sort(rng.choice(np.arange(3000, 5000), 64, replace=False))
-    dirs = [rng.normal(size=p.n) * (p.wp2 > 0) for _ in range(4)]
+    dirs = [np.clip(rng.normal(size=p.n), -3, 3) for _ in range(4)]
     say(f"case c5 adjoint fp32 n={p.n} steps={T}: vacuum reference")
     with G.FdtdPlasma(p.vacuum(), precision="f64", exec="tiled") as hv:
         hv.run(T)
@@ -128,8 +133,9 @@ def test_c5_fp32_adjoint_vs_fd_and_oracle(G):
     assert rel <= 1e-4
     big = np.abs(fd) >= 1e-2 * np.max(np.abs(fd))
     assert np.all(np.abs(g32[cells][big] - fd[big]) <= 1e-4 * np.abs(fd[big]) + 1e-4 * np.max(np.abs(fd)))
-    proj = np.array([g32 @ v for v in dirs])
-    assert np.max(np.abs(proj - fdd) / np.abs(fdd)) <= 1e-4
+    proj = np.array([g32 @ (v * p.wp2) for v in dirs])   # d/d(eps) L(wp2 (1 + eps v))
+    say(f"c5 directional derivatives: adjoint {proj}, FD {fdd}")
+    assert np.linalg.norm(proj - fdd) <= 1e-4 * np.linalg.norm(fdd)
     say("case c5: fp64 oracle adjoint (full trajectory)")
     Lo, go, _ = oracle.adjoint_r2(p, T, xv)
     relo = np.linalg.norm(g32 - go) / np.linalg.norm(go)
