@@ -188,6 +188,33 @@ def c1_leg(reps=5):
             "exec": "resident (one workgroup)"}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    d = os.path.join(ROOT, "paper_1709_00821_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, precision, tune, cells):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on these kernel sources and this launch shape."""
+    path = os.path.join(ROOT, "profiles", "tiled_c2_f32_hbm_traffic.md")
+    try:
+        txt = open(path).read()
+        blk = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if (blk.get("source_sha256") != kernel_source_hash() or blk.get("precision") != precision
+            or blk.get("tile_cells") != tune["tile_cells"]
+            or blk.get("steps_per_pass") != tune["steps_per_pass"] or blk.get("cells") != cells):
+        return None
+    k = blk.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(p, steps):
     import oracle
     log(f"bench: cpu baseline: oracle on the full {p.n}-cell grid for {steps} steps")
@@ -271,6 +298,8 @@ def main():
     value = cells * T / (ms / 1e3) / 1e6
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     rl = alu_roofline(prof, dom, tune["steps_per_pass"])
+    hv = roofline(prof, args.precision)
+    rl["traffic"] = hv["traffic"] = counter_traffic(dom, args.precision, tune, cells)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -282,7 +311,7 @@ def main():
                    "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"],
                    "fields": args.precision, "coefficients_dft": "f64"},
         "roofline": rl,
-        "hbm_view": roofline(prof, args.precision),
+        "hbm_view": hv,
         "single_step_bound_mcells": round(HBM_PEAK_GBS * 1e9 / (
             0.5 * algorithmic_bytes_per_node(args.precision, True)
             + 0.5 * algorithmic_bytes_per_node(args.precision, False)) / 1e6, 1),
