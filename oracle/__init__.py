@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["rketd1d.c", "adjoint1d.c"]
+_SRCS = ["rketd1d.c", "adjoint1d.c", "rketd3d.c"]
 _lib = None
 
 BC = {"mur": 0, "cpml": 1, "pec": 2, "periodic": 3}
@@ -80,6 +80,8 @@ def _declare(L):
     L.or_dft_accumulate.argtypes = [i64, p, i64, ctypes.c_int, p, d, p, p]
     L.or1d_check.argtypes = [p]
     L.or1d_step.argtypes = [p, p, i64]
+    L.or3d_check.argtypes = [p]
+    L.or3d_step.argtypes = [p, p, i64]
     if hasattr(L, "or1d_adjoint_r2"):
         L.or1d_adjoint_r2.argtypes = [p, i64, ctypes.c_int32, p, p, p, p, p]
         L.or1d_adjoint_step.argtypes = [p, p, p, p]
@@ -219,3 +221,88 @@ def adjoint_r2(p, nsteps: int, xv: np.ndarray, probe: int = 0):
     if rc != 0:
         raise ValueError(f"oracle adjoint rejected the problem (code {rc})")
     return loss.value, grad, X[:F] + 1j * X[F:]
+
+
+# ---------------------------------------------------------------------------
+# 3D (rketd3d.c)
+# ---------------------------------------------------------------------------
+
+class _Problem3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+        ("d", ctypes.c_double), ("dt", ctypes.c_double),
+        ("wp2", ctypes.c_void_p * 3), ("nu", ctypes.c_void_p * 3),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("cpml", ctypes.c_int64), ("source", ctypes.c_int32), ("src_comp", ctypes.c_int32),
+        ("src_k", ctypes.c_int64), ("src_tau", ctypes.c_double), ("src_t0", ctypes.c_double),
+        ("src_amp", ctypes.c_double), ("b0", ctypes.c_int64), ("b1", ctypes.c_int64),
+        ("naux", ctypes.c_int64), ("aux_off", ctypes.c_int64), ("aux_src", ctypes.c_int64),
+        ("n_points", ctypes.c_int32), ("n_freqs", ctypes.c_int32),
+        ("points", ctypes.c_void_p), ("freqs", ctypes.c_void_p),
+    ]
+
+
+class _State3(ctypes.Structure):
+    _fields_ = [
+        ("E", ctypes.c_void_p * 3), ("H", ctypes.c_void_p * 3), ("J", ctypes.c_void_p * 3),
+        ("psi", ctypes.c_void_p), ("Einc", ctypes.c_void_p), ("Hinc", ctypes.c_void_p),
+        ("Xre", ctypes.c_void_p), ("Xim", ctypes.c_void_p), ("step", ctypes.c_int64),
+    ]
+
+
+SOURCE3 = {"none": 0, "planar": 1, "tfsf": 2}
+
+
+def _problem3(p, keep: _Keep) -> _Problem3:
+    wp2 = [keep.arr(p.wp2[c], np.float64) for c in range(3)]
+    nu = [keep.arr(p.nu_comp(c), np.float64) for c in range(3)]
+    pts = keep.arr(np.asarray(p.points, np.int32).reshape(-1, 4), np.int32)
+    freqs = keep.arr(p.freqs, np.float64)
+    naux, aoff, asrc = p.aux_layout() if p.source == "tfsf" else (0, 0, 0)
+    return _Problem3(
+        nx=p.nx, ny=p.ny, nz=p.nz, d=p.d, dt=p.dt,
+        wp2=(ctypes.c_void_p * 3)(*[_ptr(a) for a in wp2]),
+        nu=(ctypes.c_void_p * 3)(*[_ptr(a) for a in nu]),
+        periodic_x=int(p.periodic_x), periodic_y=int(p.periodic_y), cpml=p.cpml,
+        source=SOURCE3[p.source], src_comp=p.src_comp, src_k=p.src_k,
+        src_tau=p.src_tau, src_t0=p.src_t0, src_amp=p.src_amp, b0=p.b0, b1=p.b1,
+        naux=naux, aux_off=aoff, aux_src=asrc, n_points=len(pts), n_freqs=len(freqs),
+        points=_ptr(pts), freqs=_ptr(freqs))
+
+
+def new_state3(p) -> dict:
+    shp = (3, p.nx, p.ny, p.nz)
+    naux = p.aux_layout()[0] if p.source == "tfsf" else 1
+    return {"E": np.zeros(shp), "H": np.zeros(shp), "J": np.zeros(shp),
+            "psi": np.zeros((12, p.nx, p.ny, p.nz)) if p.cpml > 0 else np.zeros(1),
+            "Einc": np.zeros(naux), "Hinc": np.zeros(naux),
+            "X": np.zeros((len(p.points), len(p.freqs)), np.complex128), "step": 0}
+
+
+def check3(p) -> int:
+    keep = _Keep()
+    return lib().or3d_check(ctypes.byref(_problem3(p, keep)))
+
+
+def run3d(p, nsteps: int, state: Optional[dict] = None) -> dict:
+    """Advance a 3D state (default: zero fields at step 0) by nsteps; returns a
+    new dict with E, H, J [3, nx, ny, nz], psi, Einc, Hinc, X [points, freqs]."""
+    st = new_state3(p) if state is None else {k: (v.copy() if isinstance(v, np.ndarray) else v)
+                                             for k, v in state.items()}
+    keep = _Keep()
+    pb = _problem3(p, keep)
+    for k in ("E", "H", "J", "psi", "Einc", "Hinc"):
+        st[k] = np.ascontiguousarray(st[k], np.float64)
+    Xre = np.ascontiguousarray(st["X"].real)
+    Xim = np.ascontiguousarray(st["X"].imag)
+    arr3 = lambda a: (ctypes.c_void_p * 3)(*[a[c].ctypes.data for c in range(3)])
+    cs = _State3(E=arr3(st["E"]), H=arr3(st["H"]), J=arr3(st["J"]),
+                 psi=_ptr(st["psi"]) if p.cpml > 0 else None,
+                 Einc=_ptr(st["Einc"]), Hinc=_ptr(st["Hinc"]),
+                 Xre=_ptr(Xre), Xim=_ptr(Xim), step=st["step"])
+    rc = lib().or3d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
+    if rc != 0:
+        raise ValueError(f"3D oracle rejected the problem (code {rc})")
+    st["X"] = Xre + 1j * Xim
+    st["step"] = cs.step
+    return st

@@ -56,6 +56,36 @@ int or1d_adjoint_r2(const or1d_problem *pb, int64_t nsteps, int32_t probe,
                     const double *xv_re, const double *xv_im, double *loss,
                     double *grad, double *X);
 
+/* ---- 3D (see rketd3d.c) ---- */
+typedef struct {
+    int64_t nx, ny, nz;        /* cells per axis */
+    double d, dt;              /* cubic cell side (m), time step (s) */
+    const double *wp2[3];      /* [nx*ny*nz] per E component, at its own position */
+    const double *nu[3];       /* [nx*ny*nz] per E component */
+    int32_t periodic_x, periodic_y;
+    int64_t cpml;              /* CPML cells per walled end (0: bare PEC walls) */
+    int32_t source;            /* 0 none, 1 planar soft source, 2 TF/SF plane wave */
+    int32_t src_comp;          /* planar source: 0 Ex, 1 Ey */
+    int64_t src_k;             /* planar source plane */
+    double src_tau, src_t0, src_amp;
+    int64_t b0, b1;            /* TF box [b0, b1] on walled axes and z */
+    int64_t naux, aux_off, aux_src;   /* incident 1D grid */
+    int32_t n_points, n_freqs;
+    const int32_t *points;     /* [n_points][4]: component (0..2 Ex..Ez, 3..5 Hx..Hz), i, j, k */
+    const double *freqs;       /* Hz */
+} or3d_problem;
+
+typedef struct {
+    double *E[3], *H[3], *J[3];   /* [nx*ny*nz] each */
+    double *psi;                  /* [12][nx*ny*nz] CPML auxiliaries (NULL if cpml == 0) */
+    double *Einc, *Hinc;          /* [naux] incident grid (NULL unless source == 2) */
+    double *Xre, *Xim;            /* [n_points][n_freqs] */
+    int64_t step;
+} or3d_state;
+
+int or3d_check(const or3d_problem *pb);
+int or3d_step(const or3d_problem *pb, or3d_state *st, int64_t nsteps);
+
 #ifdef __cplusplus
 }
 #endif

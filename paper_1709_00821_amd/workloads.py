@@ -213,3 +213,143 @@ def light_cone(p: Problem1D, steps: int, extra: int = 2) -> Optional[tuple]:
     if lo <= 0 or hi >= p.n:
         return None
     return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# 3D problems (Yee lattice, cubic cells; components at their staggered
+# positions, arrays [i][j][k] with k fastest)
+# ---------------------------------------------------------------------------
+
+# component codes of sample points: E then H
+COMPONENTS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+# half-cell offsets of each component's position, (x, y, z)
+STAGGER = {
+    "Ex": (0.5, 0.0, 0.0), "Ey": (0.0, 0.5, 0.0), "Ez": (0.0, 0.0, 0.5),
+    "Hx": (0.0, 0.5, 0.5), "Hy": (0.5, 0.0, 0.5), "Hz": (0.5, 0.5, 0.0),
+}
+
+# incident-grid margin of the TF/SF source: the 1D grid spans z in
+# [b0 - AUX_MARGIN, b1 + AUX_MARGIN] with its soft source AUX_SRC nodes in
+AUX_MARGIN = 8
+AUX_SRC = 3
+
+
+@dataclasses.dataclass
+class Problem3D:
+    nx: int
+    ny: int
+    nz: int
+    d: float
+    dt: float
+    wp2: np.ndarray                   # [3, nx, ny, nz] float64 per E component
+    nu: np.ndarray                    # [3, nx, ny, nz] or [nx, ny, nz] (shared)
+    src_tau: float
+    src_t0: float
+    src_amp: float
+    freqs: np.ndarray
+    points: np.ndarray                # int32 [n, 4]: component code, i, j, k
+    periodic_x: bool = False
+    periodic_y: bool = False
+    cpml: int = 0
+    source: str = "none"              # "none" | "planar" | "tfsf"
+    src_comp: int = 0                 # planar source: 0 Ex, 1 Ey
+    src_k: int = 0
+    b0: int = 0                       # TF box [b0, b1]
+    b1: int = 0
+    steps: int = 0
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def nu_comp(self, c: int) -> np.ndarray:
+        return self.nu[c] if self.nu.ndim == 4 else self.nu
+
+    def aux_layout(self):
+        """(naux, aux_off, aux_src) of the incident 1D grid: aux node q is at
+        z = q - aux_off."""
+        naux = self.b1 - self.b0 + 2 * AUX_MARGIN + 1
+        return naux, AUX_MARGIN - self.b0, AUX_SRC
+
+    def vacuum(self) -> "Problem3D":
+        return dataclasses.replace(self, wp2=np.zeros_like(self.wp2))
+
+    def copy(self, **kw) -> "Problem3D":
+        return dataclasses.replace(self, **kw)
+
+
+def box_points(lo: int, hi: int, nx: int, ny: int, nz: int) -> np.ndarray:
+    """Sample points on the six faces of the box [lo, hi]^3: on each face the
+    four field components tangential to it at the face's index (face x = lo:
+    Ey, Ez, Hy, Hz with i = lo), over the nodes whose other two coordinates
+    lie in [lo, hi].  E nodes lie in the face plane, H nodes half a cell
+    towards +axis.  Faces
+    in the order x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; within a face component by
+    component, nodes in [i][j][k] order."""
+    if not (0 <= lo < hi < min(nx, ny, nz)):
+        raise ValueError("box outside the grid")
+    tang = {0: ("Ey", "Ez", "Hy", "Hz"), 1: ("Ex", "Ez", "Hx", "Hz"), 2: ("Ex", "Ey", "Hx", "Hy")}
+    out = []
+    for axis in range(3):
+        for face in (lo, hi):
+            for name in tang[axis]:
+                off = STAGGER[name]
+                rng_ = []
+                for a in range(3):
+                    if a == axis:
+                        rng_.append(np.array([face]))
+                    else:
+                        # nodes whose position lies within [lo, hi]
+                        top = hi - 1 if off[a] == 0.5 else hi
+                        rng_.append(np.arange(lo, top + 1))
+                I, J, K = np.meshgrid(*rng_, indexing="ij")
+                c = np.full(I.size, COMPONENTS.index(name))
+                out.append(np.stack([c, I.ravel(), J.ravel(), K.ravel()], axis=1))
+    return np.ascontiguousarray(np.concatenate(out), np.int32)
+
+
+def sphere_wp2(nx: int, ny: int, nz: int, centre, radius: float, cutoff: float,
+               wp2_peak: float) -> np.ndarray:
+    """wp^2(r) = peak exp(-(r/radius)^2) for r <= cutoff (cells), else 0,
+    sampled at each E component's own position; [3, nx, ny, nz]."""
+    out = np.zeros((3, nx, ny, nz))
+    c = np.asarray(centre, np.float64)
+    lo = [max(0, int(math.floor(c[a] - cutoff - 1))) for a in range(3)]
+    hi = [min(n, int(math.ceil(c[a] + cutoff + 1)) + 1) for a, n in enumerate((nx, ny, nz))]
+    for comp, name in enumerate(("Ex", "Ey", "Ez")):
+        off = STAGGER[name]
+        x = np.arange(lo[0], hi[0]) + off[0] - c[0]
+        y = np.arange(lo[1], hi[1]) + off[1] - c[1]
+        z = np.arange(lo[2], hi[2]) + off[2] - c[2]
+        r2 = x[:, None, None] ** 2 + y[None, :, None] ** 2 + z[None, None, :] ** 2
+        v = wp2_peak * np.exp(-r2 / radius ** 2)
+        v[r2 > cutoff ** 2] = 0.0
+        out[comp, lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = v
+    return out
+
+
+def sphere_c3(n: int = 384, steps: int = 2000, d: float = 0.5e-3, courant: float = 0.5,
+              n_freqs: int = 16, cpml: int = 10, tf: Optional[tuple] = None,
+              box: Optional[tuple] = None, box_dft: bool = True) -> Problem3D:
+    """Plasma sphere in a TF/SF plane wave: n^3 cells of d = 0.5 mm at Courant
+    number c dt / d = 0.5; wp^2 = (2 pi 20 GHz)^2 exp(-(r/R)^2) for r <= 1.5 R,
+    R = n/4, centred; nu = 10 GHz; x-polarised +z plane wave with the eq.(15)
+    pulse; CPML of `cpml` cells on every face; TF box faces at 18 and n - 19
+    (scaled for other n); FP64 DFT at 16 frequencies over 2-40 GHz of the
+    tangential E and H on a box in the scattered-field region, midway between
+    the CPML and the TF box (faces at 14 and 369 for n = 384)."""
+    dt = courant * d / C0
+    tau, t0, amp = pulse_params(dt)
+    R = n / 4.0
+    wp2 = sphere_wp2(n, n, n, (n / 2.0,) * 3, R, 1.5 * R, (2 * math.pi * 20 * GHZ) ** 2)
+    nu = np.full((n, n, n), 1e10)
+    if tf is None:
+        tf = (max(cpml + 2, round(18 * n / 384)), n - max(cpml + 3, round(19 * n / 384)))
+    if box is None:       # midway between the CPML and the TF box
+        box = ((cpml + tf[0]) // 2, (tf[1] + n - cpml) // 2)
+    pts = box_points(box[0], box[1], n, n, n) if box_dft else np.zeros((0, 4), np.int32)
+    freqs = np.linspace(2 * GHZ, 40 * GHZ, n_freqs)
+    return Problem3D(nx=n, ny=n, nz=n, d=d, dt=dt, wp2=wp2, nu=nu, src_tau=tau,
+                     src_t0=t0, src_amp=amp, freqs=freqs, points=pts, cpml=cpml,
+                     source="tfsf", b0=int(tf[0]), b1=int(tf[1]), steps=steps)
