@@ -15,6 +15,7 @@ import torch  # noqa: F401  (must precede loading the HIP library)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd_plasma.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fdtd_plasma.h")
+HEADER3 = os.path.join(os.path.dirname(HERE), "include", "fdtd_plasma3d.h")
 
 # status codes and enums (include/fdtd_plasma.h)
 OK, E_INVALID, E_UNSTABLE, E_WORKSPACE, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPPORTED = \
@@ -63,6 +64,35 @@ class Desc(ctypes.Structure):
     ]
 
 
+class Desc3(ctypes.Structure):
+    """fdtd3d_desc (include/fdtd_plasma3d.h)."""
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+        ("d", ctypes.c_double), ("dt", ctypes.c_double),
+        ("wp2", ctypes.c_void_p * 3),
+        ("nu", ctypes.c_void_p * 3),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("cpml_cells", ctypes.c_int32),
+        ("source", ctypes.c_int32),
+        ("src_comp", ctypes.c_int32),
+        ("src_k", ctypes.c_int64),
+        ("src_tau", ctypes.c_double), ("src_t0", ctypes.c_double), ("src_amp", ctypes.c_double),
+        ("tf_lo", ctypes.c_int64), ("tf_hi", ctypes.c_int64),
+        ("n_points", ctypes.c_int32), ("n_freqs", ctypes.c_int32),
+        ("points", ctypes.c_void_p),
+        ("freqs_hz", ctypes.c_void_p),
+        ("sample_slots", ctypes.c_int32),
+        ("exec", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+SRC3 = {"none": 0, "planar": 1, "tfsf": 2}
+EXEC3 = {"auto": 0, "split": 1, "fused": 2}
+FIELDS3 = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz")
+
 _lib = None
 
 
@@ -87,6 +117,17 @@ def lib():
             "fdtd_plasma_loss_r2": [p, i32, p, p, p],
             "fdtd_plasma_profile": [p, i64, i32, p, p, p, p, p],
             "fdtd_plasma_destroy": [p],
+            "fdtd3d_workspace_bytes": [p, p],
+            "fdtd3d_create": [p, p, ctypes.c_size_t, p],
+            "fdtd3d_step": [p, i64],
+            "fdtd3d_run": [p, i64],
+            "fdtd3d_spectra": [p, p, p],
+            "fdtd3d_get_fields": [p, i32, p],
+            "fdtd3d_set_fields": [p, i32, p],
+            "fdtd3d_steps_done": [p, p],
+            "fdtd3d_profile": [p, i32],
+            "fdtd3d_profile_read": [p, i32, p, p, p, p, p],
+            "fdtd3d_destroy": [p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -94,6 +135,8 @@ def lib():
             fn.restype = ctypes.c_int
         L.fdtd_plasma_last_error.argtypes = []
         L.fdtd_plasma_last_error.restype = ctypes.c_char_p
+        L.fdtd3d_last_error.argtypes = []
+        L.fdtd3d_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -105,7 +148,14 @@ def check(rc: int):
     return rc
 
 
+def check3(rc: int):
+    if rc != OK:
+        msg = lib().fdtd3d_last_error().decode(errors="replace")
+        raise FdtdError(rc, msg)
+    return rc
+
+
 def header_symbols(path: str = HEADER):
-    """Function names the public header declares."""
+    """Function names a public header declares."""
     txt = open(path).read()
-    return sorted(set(re.findall(r"\b(fdtd_plasma_[a-z0-9_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(fdtd(?:_plasma|3d)_[a-z0-9_]+)\s*\(", txt)))

@@ -1,0 +1,589 @@
+// 3D Yee-RKETD kernels.  One time step is either
+//   k_h3d   H^{n+1/2} from E^n (CPML auxiliaries, TF/SF H corrections fused)
+//   k_aux3d the incident 1D grid (TF/SF only): H^{n+1/2}, E^{n+1}, source, Mur
+//   k_e3d   E^{n+1} (CPML, TF/SF E corrections or the planar source, PEC walls)
+//           and J^{n+1} on the plasma support, fused
+// (two passes over the grid, in place), or k_aux3d + k_fused3d (one pass,
+// E/H/CPML ping-pong); both call the same per-cell h_cell / e_cell and give
+// identical bits.  Then
+//   k_sample3d  the sample points into the current slot of the sample buffer
+// and every `slots` steps k_tw3d + k_flush3d fold the buffered samples into the
+// FP64 DFT accumulators.
+//
+// The update formulas are the 1D library's per-node physics (physics.h): H by
+// one FMA per component, E in vacuum by one FMA, plasma E by the solved
+// eqs.(11)+(12) (FP32: delta form around CA - 1), J by eq.(11) in FP64.
+#include <hip/hip_runtime.h>
+
+#include "internal3d.h"
+
+namespace fdtdp {
+
+namespace {
+
+// Consecutive logical blocks on one XCD: the hardware deals workgroups to the
+// 8 XCDs round-robin, so hardware block b runs on XCD b % 8; give that XCD the
+// b / 8-th block of its own contiguous chunk.  Neighbouring i-planes then share
+// an L2.
+__device__ __forceinline__ int64_t xcd_chunk(int64_t bid, int64_t nblk)
+{
+    const int64_t q = nblk / 8, r = nblk % 8;
+    const int64_t x = bid % 8, j = bid / 8;
+    return x * q + (x < r ? x : r) + j;
+}
+
+struct Cell {
+    int64_t i, j, k, p;
+    bool ok;
+};
+
+__device__ __forceinline__ Cell cell_of(const Geo3 &g)
+{
+    Cell c;
+    const int64_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+    const int64_t kq = bid % g.kb, r = bid / g.kb;
+    c.j = (r % g.jb) * 4 + (threadIdx.x >> 6);
+    c.i = r / g.jb;
+    c.k = kq * 64 + (threadIdx.x & 63);
+    c.ok = c.j < g.ny && c.k < g.nz;
+    c.p = (c.i * g.ny + c.j) * g.nz + c.k;
+    return c;
+}
+
+// slab index of node n on an axis of `len` nodes with P-node layers, or -1
+__device__ __forceinline__ int64_t slab(int64_t n, int64_t len, int P)
+{
+    if (n < P) return n;
+    if (n >= len - P) return n - (len - 2 * P);
+    return -1;
+}
+
+// psi' = b psi + a dF (separately rounded, as written), stored only by the
+// cell's owner; returns dF + psi'
+template <typename T>
+__device__ __forceinline__ T cpml_term(const T *pin, T *pout, int64_t idx, T b, T a, T dF, bool store)
+{
+    const T v = b * pin[idx] + a * dF;
+    if (store) pout[idx] = v;
+    return dF + v;
+}
+
+}  // namespace
+
+// H^{n+1/2} of cell (i, j, k) from its E^n and the E^n of its +1 neighbours
+// (zero beyond a wall); hx, hy, hz hold H^{n-1/2} on entry.  CPML auxiliaries
+// and the TF/SF correction (Einc^n) included.  Shared by both executors.
+template <typename T>
+__device__ __forceinline__ void h_cell(const Geo3 &g, const Cpml3<T> &c, const double *Einc, int64_t i,
+                                       int64_t j, int64_t k, T ex, T ey, T ez, T ex_j, T ex_k, T ey_i,
+                                       T ey_k, T ez_i, T ez_j, T &hx, T &hy, T &hz, bool store)
+{
+    T dEz_y = ez_j - ez;
+    T dEy_z = ey_k - ey;
+    T dEx_z = ex_k - ex;
+    T dEz_x = ez_i - ez;
+    T dEy_x = ey_i - ey;
+    T dEx_y = ex_j - ex;
+    if (g.P > 0) {
+        const int P = g.P, P2 = 2 * g.P;
+        if (!g.px) {
+            const int64_t s = slab(i, g.nx, P);
+            if (s >= 0) {
+                const int64_t id = (s * g.ny + j) * g.nz + k;
+                const T b = c.tab[(0 * 4 + 2) * P2 + s], a = c.tab[(0 * 4 + 3) * P2 + s];
+                dEz_x = cpml_term(c.inH[0][0], c.outH[0][0], id, b, a, dEz_x, store);
+                dEy_x = cpml_term(c.inH[0][1], c.outH[0][1], id, b, a, dEy_x, store);
+            }
+        }
+        if (!g.py) {
+            const int64_t s = slab(j, g.ny, P);
+            if (s >= 0) {
+                const int64_t id = (i * P2 + s) * g.nz + k;
+                const T b = c.tab[(1 * 4 + 2) * P2 + s], a = c.tab[(1 * 4 + 3) * P2 + s];
+                dEz_y = cpml_term(c.inH[1][0], c.outH[1][0], id, b, a, dEz_y, store);
+                dEx_y = cpml_term(c.inH[1][1], c.outH[1][1], id, b, a, dEx_y, store);
+            }
+        }
+        const int64_t s = slab(k, g.nz, P);
+        if (s >= 0) {
+            const int64_t id = (i * g.ny + j) * P2 + s;
+            const T b = c.tab[(2 * 4 + 2) * P2 + s], a = c.tab[(2 * 4 + 3) * P2 + s];
+            dEy_z = cpml_term(c.inH[2][0], c.outH[2][0], id, b, a, dEy_z, store);
+            dEx_z = cpml_term(c.inH[2][1], c.outH[2][1], id, b, a, dEx_z, store);
+        }
+    }
+    const T ch = (T)g.chd;
+    hx = fmat(-ch, dEz_y - dEy_z, hx);
+    hy = fmat(-ch, dEx_z - dEz_x, hy);
+    hz = fmat(-ch, dEy_x - dEx_y, hz);
+    if (g.src == 2) {
+        // scattered H beside the box reads total Ex across a face: remove the
+        // incident part (Einc^n).  Hy(k+1/2) at k = b0-1 and b1; Hz(j+1/2) at
+        // j = b0-1 and b1 (walled y), with the minus sign of dEx/dy in curl_z.
+        const bool inx = i >= g.xlo && i < g.xhi;
+        if (inx && j >= g.ylo && j < g.yhi) {
+            if (k == g.b0 - 1) hy = hy + (T)(g.chd * Einc[g.b0 + g.ao]);
+            else if (k == g.b1) hy = hy - (T)(g.chd * Einc[g.b1 + g.ao]);
+        }
+        if (!g.py && inx && k >= g.b0 && k <= g.b1) {
+            if (j == g.b0 - 1) hz = hz - (T)(g.chd * Einc[k + g.ao]);
+            else if (j == g.b1) hz = hz + (T)(g.chd * Einc[k + g.ao]);
+        }
+    }
+}
+
+// Plasma node coefficients of one component (FP64 CH kept for the TF/SF term).
+template <typename T>
+__device__ __forceinline__ NodeCoef<T> coef3(double wp2, double nu, double dt, double d, double &CH)
+{
+    const Coef c = node_coef(wp2, nu, dt, d, 0);
+    NodeCoef<T> r;
+    r.eA = sizeof(T) == 8 ? (T)c.CA : (T)c.CAm1;
+    r.eJ = (T)c.CJ;
+    r.eH = (T)c.CH;
+    r.a = c.a;
+    r.b1 = c.b1;
+    r.b2 = c.b2;
+    CH = c.CH;
+    return r;
+}
+
+// E update with the 3D curl sign: E_new = CA E - CJ J + CH curl.
+__device__ __forceinline__ double e_plasma3(double E, double J, double curl, const NodeCoef<double> &c)
+{
+    return fmat(c.eH, curl, fmat(-c.eJ, J, c.eA * E));
+}
+__device__ __forceinline__ float e_plasma3(float E, float J, float curl, const NodeCoef<float> &c)
+{
+    return fmat(c.eH, curl, fmat(-c.eJ, J, fmat(c.eA, E, E)));
+}
+
+// E^{n+1} of cell (i, j, k) from its H^{n+1/2} and the H^{n+1/2} of its -1
+// neighbours (zero beyond a wall); e0..e2 hold E^n on entry.  CPML, TF/SF (or
+// the planar source), PEC walls and, on the plasma support, J^{n+1} (written
+// in place).  Shared by both executors.
+template <typename T>
+__device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, const Cpml3<T> &c,
+                                       const double *Hinc, double sval, int64_t i, int64_t j, int64_t k,
+                                       T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
+                                       T &e0, T &e1, T &e2)
+{
+    const T zero = (T)0;
+    T dHz_y = hz - hz_j;
+    T dHy_z = hy - hy_k;
+    T dHx_z = hx - hx_k;
+    T dHz_x = hz - hz_i;
+    T dHy_x = hy - hy_i;
+    T dHx_y = hx - hx_j;
+    if (g.P > 0) {
+        const int P = g.P, P2 = 2 * g.P;
+        if (!g.px) {
+            const int64_t s = slab(i, g.nx, P);
+            if (s >= 0) {
+                const int64_t id = (s * g.ny + j) * g.nz + k;
+                const T b = c.tab[(0 * 4 + 0) * P2 + s], a = c.tab[(0 * 4 + 1) * P2 + s];
+                dHz_x = cpml_term(c.inE[0][0], c.outE[0][0], id, b, a, dHz_x, true);
+                dHy_x = cpml_term(c.inE[0][1], c.outE[0][1], id, b, a, dHy_x, true);
+            }
+        }
+        if (!g.py) {
+            const int64_t s = slab(j, g.ny, P);
+            if (s >= 0) {
+                const int64_t id = (i * P2 + s) * g.nz + k;
+                const T b = c.tab[(1 * 4 + 0) * P2 + s], a = c.tab[(1 * 4 + 1) * P2 + s];
+                dHz_y = cpml_term(c.inE[1][0], c.outE[1][0], id, b, a, dHz_y, true);
+                dHx_y = cpml_term(c.inE[1][1], c.outE[1][1], id, b, a, dHx_y, true);
+            }
+        }
+        const int64_t s = slab(k, g.nz, P);
+        if (s >= 0) {
+            const int64_t id = (i * g.ny + j) * P2 + s;
+            const T b = c.tab[(2 * 4 + 0) * P2 + s], a = c.tab[(2 * 4 + 1) * P2 + s];
+            dHy_z = cpml_term(c.inE[2][0], c.outE[2][0], id, b, a, dHy_z, true);
+            dHx_z = cpml_term(c.inE[2][1], c.outE[2][1], id, b, a, dHx_z, true);
+        }
+    }
+    const T curl0 = dHz_y - dHy_z, curl1 = dHx_z - dHz_x, curl2 = dHy_x - dHx_y;
+    const T eo0 = e0, eo1 = e1, eo2 = e2;
+    const int64_t row = i * g.ny + j;
+    const int2 sp = pl.span[row];
+    const bool plasma = k >= sp.x && k < sp.y;
+    double CH0 = g.ced, CH2 = g.ced;
+    NodeCoef<T> c0, c1, c2;
+    int64_t cq = 0;
+    if (!plasma) {
+        const T ce = (T)g.ced;
+        e0 = fmat(ce, curl0, eo0);
+        e1 = fmat(ce, curl1, eo1);
+        e2 = fmat(ce, curl2, eo2);
+    } else {
+        cq = pl.off[row] + (k - sp.x);
+        double CH1;
+        c0 = coef3<T>(pl.wp2[0][cq], pl.nu[0][cq], g.dt, g.d, CH0);
+        c1 = coef3<T>(pl.wp2[1][cq], pl.nu[1][cq], g.dt, g.d, CH1);
+        c2 = coef3<T>(pl.wp2[2][cq], pl.nu[2][cq], g.dt, g.d, CH2);
+        e0 = e_plasma3(eo0, pl.J[0][cq], curl0, c0);
+        e1 = e_plasma3(eo1, pl.J[1][cq], curl1, c1);
+        e2 = e_plasma3(eo2, pl.J[2][cq], curl2, c2);
+    }
+    if (g.src == 2) {
+        // total E on a box face reads scattered H outside it: add the incident
+        // part (Hinc^{n+1/2}).  Ex at k = b0, b1; Ez at i = b0, b1 (walled x).
+        if (i >= g.xlo && i < g.xhi && j >= g.ylo && j < g.yhi) {
+            if (k == g.b0) e0 = e0 + (T)(CH0 * Hinc[g.b0 - 1 + g.ao]);
+            else if (k == g.b1) e0 = e0 - (T)(CH0 * Hinc[g.b1 + g.ao]);
+        }
+        if (!g.px && j >= g.ylo && j < g.yhi && k >= g.b0 && k < g.b1) {
+            if (i == g.b0) e2 = e2 - (T)(CH2 * Hinc[k + g.ao]);
+            else if (i == g.b1) e2 = e2 + (T)(CH2 * Hinc[k + g.ao]);
+        }
+    } else if (g.src == 1 && k == g.src_k) {
+        if (g.src_comp == 0) e0 = add_source(e0, sval);
+        else e1 = add_source(e1, sval);
+    }
+    // PEC: tangential E on the index-0 faces of walled axes
+    if (!g.px && i == 0) { e1 = zero; e2 = zero; }
+    if (!g.py && j == 0) { e0 = zero; e2 = zero; }
+    if (k == 0) { e0 = zero; e1 = zero; }
+    if (plasma) {
+        pl.J[0][cq] = j_update<T>(pl.J[0][cq], eo0, e0, c0);
+        pl.J[1][cq] = j_update<T>(pl.J[1][cq], eo1, e1, c1);
+        pl.J[2][cq] = j_update<T>(pl.J[2][cq], eo2, e2, c2);
+    }
+}
+
+// ---- two-kernel step (in place) --------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_h3d(Geo3 g, Fields3<T> f, Cpml3<T> c, const double *Einc)
+{
+    const Cell q = cell_of(g);
+    if (!q.ok) return;
+    const int64_t i = q.i, j = q.j, k = q.k, p = q.p;
+    const int64_t sI = g.ny * g.nz, sJ = g.nz;
+    const T *Ex = f.E[0], *Ey = f.E[1], *Ez = f.E[2];
+    // +1 neighbours: periodic wrap, or zero beyond a wall (loads stay in bounds)
+    const bool hasi = g.px || i + 1 < g.nx, hasj = g.py || j + 1 < g.ny, hask = k + 1 < g.nz;
+    const int64_t ip = i + 1 < g.nx ? p + sI : p - i * sI;
+    const int64_t jp = j + 1 < g.ny ? p + sJ : p - j * sJ;
+    const int64_t kp = hask ? p + 1 : p;
+    const T zero = (T)0;
+    const T ez_j = Ez[jp], ey_k = Ey[kp], ex_k = Ex[kp], ez_i = Ez[ip], ey_i = Ey[ip], ex_j = Ex[jp];
+    T hx = f.H[0][p], hy = f.H[1][p], hz = f.H[2][p];
+    h_cell<T>(g, c, Einc, i, j, k, Ex[p], Ey[p], Ez[p], hasj ? ex_j : zero, hask ? ex_k : zero,
+              hasi ? ey_i : zero, hask ? ey_k : zero, hasi ? ez_i : zero, hasj ? ez_j : zero, hx, hy, hz, true);
+    f.H[0][p] = hx;
+    f.H[1][p] = hy;
+    f.H[2][p] = hz;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_e3d(Geo3 g, Fields3<T> f, Plasma3<T> pl, Cpml3<T> c,
+                                             const double *Hinc, double sval)
+{
+    const Cell q = cell_of(g);
+    if (!q.ok) return;
+    const int64_t i = q.i, j = q.j, k = q.k, p = q.p;
+    const int64_t sI = g.ny * g.nz, sJ = g.nz;
+    const T *Hx = f.H[0], *Hy = f.H[1], *Hz = f.H[2];
+    // -1 neighbours: periodic wrap, or zero beyond a wall
+    const bool hasi = g.px || i > 0, hasj = g.py || j > 0, hask = k > 0;
+    const int64_t im = i > 0 ? p - sI : p + (g.nx - 1) * sI;
+    const int64_t jm = j > 0 ? p - sJ : p + (g.ny - 1) * sJ;
+    const int64_t km = hask ? p - 1 : p;
+    const T zero = (T)0;
+    const T hz_j = Hz[jm], hy_k = Hy[km], hx_k = Hx[km], hz_i = Hz[im], hy_i = Hy[im], hx_j = Hx[jm];
+    T e0 = f.E[0][p], e1 = f.E[1][p], e2 = f.E[2][p];
+    e_cell<T>(g, pl, c, Hinc, sval, i, j, k, Hx[p], Hy[p], Hz[p], hasj ? hx_j : zero, hask ? hx_k : zero,
+              hasi ? hy_i : zero, hask ? hy_k : zero, hasi ? hz_i : zero, hasj ? hz_j : zero, e0, e1, e2);
+    f.E[0][p] = e0;
+    f.E[1][p] = e1;
+    f.E[2][p] = e2;
+}
+
+// ---- fused step ---------------------------------------------------------------
+//
+// One workgroup owns a 64 (k) x 4 (j) column of cells over a chunk of planes
+// [i0, i1) and marches along i.  Per plane it stages E^n of the tile plus a
+// one-cell rim (rows j0-1 .. j0+4, columns k0-1 .. k0+64) in LDS, computes
+// H^{n+1/2} on the tile plus its low rim (row j0-1, column k0-1, recomputed
+// from E^n exactly as their owners do, written back only by the owner), then
+// E^{n+1} and J^{n+1} of the tile from the H of this plane and the previous
+// one.  The chunk starts one plane early (i0-1) to produce the H its first E
+// plane needs.  E, H and the CPML auxiliaries are read from one copy and
+// written to the other, so no workgroup reads a value another has already
+// advanced.  HBM traffic per cell: E and H read once, written once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fused3d(Geo3 g, Fields3<T> fin, Fields3<T> fout, Plasma3<T> pl,
+                                                 Cpml3<T> c, const double *Einc, const double *Hinc,
+                                                 double sval, int ni)
+{
+    constexpr int TJ = kFusedRows, NT = TJ * 64;
+    constexpr int PJ = TJ + 2, PK = 66;        // E patch: rows j0-1 .. j0+TJ, cols k0-1 .. k0+64
+    constexpr int HJ = TJ + 1, HK = 65;        // H patch: rows j0-1 .. j0+TJ-1, cols k0-1 .. k0+63
+    __shared__ T sE[2][3][PJ * PK];
+    __shared__ T sH[2][3][HJ * HK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t bid = xcd_chunk(blockIdx.x, gridDim.x);
+    const int64_t kq = bid % g.kb, r = bid / g.kb;
+    const int64_t j0 = (r % g.jb) * TJ, i0 = (r / g.jb) * ni, k0 = kq * 64;
+    const int64_t i1 = i0 + ni < g.nx ? i0 + ni : g.nx;
+    const T zero = (T)0;
+
+    // index along an axis: in range, wrapped (periodic), or absent (wall)
+    auto wrap = [](int64_t x, int64_t n, bool per, bool &ok) -> int64_t {
+        if (x >= 0 && x < n) { ok = true; return x; }
+        ok = per;
+        const int64_t m = x % n;            // in range even where n < the rim
+        return m < 0 ? m + n : m;
+    };
+    auto load_plane = [&](int64_t ip, int buf) {
+        bool iok;
+        const int64_t gi = wrap(ip, g.nx, g.px != 0, iok);
+        for (int e = tid; e < PJ * PK; e += NT) {
+            const int pj = e / PK, pk = e - pj * PK;
+            bool jok;
+            const int64_t gj = wrap(j0 - 1 + pj, g.ny, g.py != 0, jok);
+            const int64_t gk = k0 - 1 + pk;
+            const bool ok = iok && jok && gk >= 0 && gk < g.nz;
+            const int64_t p = ok ? (gi * g.ny + gj) * g.nz + gk : 0;
+            sE[buf][0][e] = ok ? fin.E[0][p] : zero;
+            sE[buf][1][e] = ok ? fin.E[1][p] : zero;
+            sE[buf][2][e] = ok ? fin.E[2][p] : zero;
+        }
+    };
+
+    load_plane(i0 - 1, (int)((i0 - 1) & 1));
+    for (int64_t i = i0 - 1; i < i1; ++i) {
+        const int eb = (int)(i & 1), en = (int)((i + 1) & 1);
+        load_plane(i + 1, en);
+        __syncthreads();
+        // H^{n+1/2} on the H patch of plane i
+        {
+            bool iok;
+            const int64_t gi = wrap(i, g.nx, g.px != 0, iok);
+            for (int e = tid; e < HJ * HK; e += NT) {
+                const int hj = e / HK, hk = e - hj * HK;
+                bool jok;
+                const int64_t uj = j0 - 1 + hj;
+                const int64_t gj = wrap(uj, g.ny, g.py != 0, jok);
+                const int64_t gk = k0 - 1 + hk;
+                T hx = zero, hy = zero, hz = zero;
+                if (iok && jok && gk >= 0 && gk < g.nz) {
+                    const int64_t p = (gi * g.ny + gj) * g.nz + gk;
+                    const int a = hj * PK + hk;
+                    hx = fin.H[0][p];
+                    hy = fin.H[1][p];
+                    hz = fin.H[2][p];
+                    const bool own = hj >= 1 && hk >= 1 && uj < g.ny && i >= i0;
+                    h_cell<T>(g, c, Einc, gi, gj, gk, sE[eb][0][a], sE[eb][1][a], sE[eb][2][a],
+                              sE[eb][0][a + PK], sE[eb][0][a + 1], sE[en][1][a], sE[eb][1][a + 1],
+                              sE[en][2][a], sE[eb][2][a + PK], hx, hy, hz, own);
+                    if (own) {
+                        fout.H[0][p] = hx;
+                        fout.H[1][p] = hy;
+                        fout.H[2][p] = hz;
+                    }
+                }
+                sH[eb][0][e] = hx;
+                sH[eb][1][e] = hy;
+                sH[eb][2][e] = hz;
+            }
+        }
+        __syncthreads();
+        // E^{n+1}, J^{n+1} of the tile in plane i
+        const int64_t j = j0 + w, k = k0 + lane;
+        if (i >= i0 && j < g.ny && k < g.nz) {
+            const int hp = (int)((i - 1) & 1);
+            const int a = (w + 1) * HK + lane + 1;
+            const int ae = (w + 1) * PK + lane + 1;
+            const int64_t p = (i * g.ny + j) * g.nz + k;
+            T e0 = sE[eb][0][ae], e1 = sE[eb][1][ae], e2 = sE[eb][2][ae];
+            e_cell<T>(g, pl, c, Hinc, sval, i, j, k, sH[eb][0][a], sH[eb][1][a], sH[eb][2][a],
+                      sH[eb][0][a - HK], sH[eb][0][a - 1], sH[hp][1][a], sH[eb][1][a - 1], sH[hp][2][a],
+                      sH[eb][2][a - HK], e0, e1, e2);
+            fout.E[0][p] = e0;
+            fout.E[1][p] = e1;
+            fout.E[2][p] = e2;
+        }
+        __syncthreads();
+    }
+}
+
+// Incident 1D vacuum grid, one workgroup: Hi from Ei_in, then Ei_out with the
+// source and first-order Mur ends (which read the old end values).
+__global__ __launch_bounds__(256) void k_aux3d(const double *Ei, double *Eo, double *Hi, int64_t na,
+                                               int64_t src, double chd, double ced, double cm, double s)
+{
+    for (int64_t q = threadIdx.x; q < na - 1; q += blockDim.x) Hi[q] = Hi[q] - chd * (Ei[q + 1] - Ei[q]);
+    __syncthreads();
+    for (int64_t q = threadIdx.x + 1; q < na - 1; q += blockDim.x) Eo[q] = Ei[q] - ced * (Hi[q] - Hi[q - 1]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Eo[src] = Eo[src] + s;
+        Eo[0] = Ei[1] + cm * (Eo[1] - Ei[0]);
+        Eo[na - 1] = Ei[na - 2] + cm * (Eo[na - 2] - Ei[na - 1]);
+    }
+}
+
+// Sample point code: component * N + node (component 0..2 E, 3..5 H).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample3d(Fields3<T> f, int64_t N, const int64_t *pts,
+                                                  int64_t npts, T *buf)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npts) return;
+    const int64_t code = pts[q];
+    const int c = (int)(code / N);
+    const int64_t p = code - (int64_t)c * N;
+    const T *src = c == 0 ? f.E[0] : c == 1 ? f.E[1] : c == 2 ? f.E[2] : c == 3 ? f.H[0] : c == 4 ? f.H[1] : f.H[2];
+    buf[q] = src[p];
+}
+
+// Twiddles dt e^{-j 2 pi f t} of slots 0..cnt-1 (samples m0+1 .. m0+cnt):
+// [0][s][f] for E (t = m dt), [1][s][f] for H (t = (m - 1/2) dt = (2m-1) dt/2).
+__global__ void k_tw3d(const double *freqs, int F, double dt, int64_t m0, int cnt, double2 *tw)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2LL * cnt * F) return;
+    const int kind = (int)(t / ((int64_t)cnt * F));
+    const int64_t r = t - (int64_t)kind * cnt * F;
+    const int s = (int)(r / F), fi = (int)(r % F);
+    const int64_t m = m0 + s + 1;
+    double re, im;
+    if (kind == 0) twiddle(freqs[fi] * dt, dt, m, re, im);
+    else twiddle(freqs[fi] * (0.5 * dt), dt, 2 * m - 1, re, im);
+    tw[t] = make_double2(re, im);
+}
+
+// X[f][q] += sum_s v_s tw_s,f, slots in order; one thread per point.
+template <typename T>
+__global__ __launch_bounds__(256) void k_flush3d(const T *buf, int cnt, int64_t npts, const int64_t *pts,
+                                                 int64_t N, int F, const double2 *tw, double2 *X)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npts) return;
+    const double2 *t = tw + (pts[q] >= 3 * N ? (int64_t)cnt * F : 0);
+    double v[kSlotsMax];
+#pragma unroll
+    for (int s = 0; s < kSlotsMax; ++s) v[s] = s < cnt ? (double)buf[(int64_t)s * npts + q] : 0.0;
+    for (int fi = 0; fi < F; ++fi) {
+        double2 x = X[(int64_t)fi * npts + q];
+#pragma unroll
+        for (int s = 0; s < kSlotsMax; ++s) {
+            if (s < cnt) {
+                const double2 w = t[(int64_t)s * F + fi];
+                x.x = __builtin_fma(v[s], w.x, x.x);
+                x.y = __builtin_fma(v[s], w.y, x.y);
+            }
+        }
+        X[(int64_t)fi * npts + q] = x;
+    }
+}
+
+__global__ void k_fill3d(uint4 *p, int64_t n16)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = i; j < n16; j += stride) p[j] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_copy3d(uint4 *dst, const uint4 *src, int64_t n16)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = i; j < n16; j += stride) dst[j] = src[j];
+}
+
+// ---- launchers ----------------------------------------------------------------
+
+static dim3 grid3(const Geo3 &g) { return dim3((unsigned)(g.kb * g.jb * g.nx)); }
+
+template <typename T>
+void launch_h3d(const Geo3 &g, const Fields3<T> &f, const Cpml3<T> &c, const double *Einc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_h3d<T>, grid3(g), dim3(256), 0, st, g, f, c, Einc);
+}
+
+template <typename T>
+void launch_e3d(const Geo3 &g, const Fields3<T> &f, const Plasma3<T> &pl, const Cpml3<T> &c,
+                const double *Hinc, double sval, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_e3d<T>, grid3(g), dim3(256), 0, st, g, f, pl, c, Hinc, sval);
+}
+
+void launch_aux3d(const double *Ei, double *Eo, double *Hi, int64_t na, int64_t src, double chd, double ced,
+                  double cm, double s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_aux3d, dim3(1), dim3(256), 0, st, Ei, Eo, Hi, na, src, chd, ced, cm, s);
+}
+
+template <typename T>
+void launch_fused3d(const Geo3 &g, const Fields3<T> &fin, const Fields3<T> &fout, const Plasma3<T> &pl,
+                    const Cpml3<T> &c, const double *Einc, const double *Hinc, double sval, int ni,
+                    hipStream_t st)
+{
+    const int64_t nb = g.kb * g.jb * ((g.nx + ni - 1) / ni);
+    hipLaunchKernelGGL(k_fused3d<T>, dim3((unsigned)nb), dim3(256), 0, st, g, fin, fout, pl, c, Einc, Hinc,
+                       sval, ni);
+}
+
+template <typename T>
+void launch_sample3d(const Fields3<T> &f, int64_t N, const int64_t *pts, int64_t npts, T *buf, hipStream_t st)
+{
+    if (npts <= 0) return;
+    hipLaunchKernelGGL(k_sample3d<T>, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, f, N, pts,
+                       npts, buf);
+}
+
+void launch_tw3d(const double *freqs, int F, double dt, int64_t m0, int cnt, double2 *tw, hipStream_t st)
+{
+    const int64_t n = 2LL * cnt * F;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tw3d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, freqs, F, dt, m0, cnt, tw);
+}
+
+template <typename T>
+void launch_flush3d(const T *buf, int cnt, int64_t npts, const int64_t *pts, int64_t N, int F,
+                    const double2 *tw, double2 *X, hipStream_t st)
+{
+    if (npts <= 0 || F <= 0 || cnt <= 0) return;
+    hipLaunchKernelGGL(k_flush3d<T>, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, buf, cnt, npts,
+                       pts, N, F, tw, X);
+}
+
+void launch_fill3d(void *p, int64_t bytes, hipStream_t st)
+{
+    const int64_t n16 = bytes / 16;
+    if (n16 <= 0) return;
+    int64_t nb = (n16 + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_fill3d, dim3((unsigned)nb), dim3(256), 0, st, (uint4 *)p, n16);
+}
+
+void launch_copy3d(void *dst, const void *src, int64_t bytes, hipStream_t st)
+{
+    const int64_t n16 = bytes / 16;
+    if (n16 <= 0) return;
+    int64_t nb = (n16 + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_copy3d, dim3((unsigned)nb), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src, n16);
+}
+
+#define INST3(T)                                                                                          \
+    template void launch_h3d<T>(const Geo3 &, const Fields3<T> &, const Cpml3<T> &, const double *,      \
+                                hipStream_t);                                                             \
+    template void launch_fused3d<T>(const Geo3 &, const Fields3<T> &, const Fields3<T> &,                \
+                                    const Plasma3<T> &, const Cpml3<T> &, const double *, const double *, \
+                                    double, int, hipStream_t);                                            \
+    template void launch_e3d<T>(const Geo3 &, const Fields3<T> &, const Plasma3<T> &, const Cpml3<T> &,  \
+                                const double *, double, hipStream_t);                                     \
+    template void launch_sample3d<T>(const Fields3<T> &, int64_t, const int64_t *, int64_t, T *,         \
+                                     hipStream_t);                                                        \
+    template void launch_flush3d<T>(const T *, int, int64_t, const int64_t *, int64_t, int,             \
+                                    const double2 *, double2 *, hipStream_t);
+INST3(float)
+INST3(double)
+#undef INST3
+
+}  // namespace fdtdp

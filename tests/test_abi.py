@@ -124,3 +124,85 @@ def test_create_runs_host_setup_without_gpu(L, exec_):
     h = ctypes.c_void_p()
     rc = L.lib().fdtd_plasma_create(ctypes.byref(d), None, 0, ctypes.byref(h))
     assert rc == -4 and h.value is None
+
+
+# ---- 3D library (include/fdtd_plasma3d.h) ----------------------------------
+
+def _p3(**kw):
+    from tests.test_oracle3d_pins import mk
+    base = dict(cpml=2, source="tfsf", b0=4, b1=9,
+                points=np.array([(0, 5, 5, 5), (4, 6, 5, 7)], np.int32))
+    base.update(kw)
+    return mk(12, 12, 16, **base)
+
+
+def _code3(p, **kw):
+    from paper_1709_00821_amd.plasma3d import make_desc3
+    d, keep = make_desc3(p, **kw)
+    n = ctypes.c_size_t()
+    from paper_1709_00821_amd import _lib
+    rc = _lib.lib().fdtd3d_workspace_bytes(ctypes.byref(d), ctypes.byref(n))
+    return rc, n.value, d
+
+
+def test_3d_exports_every_header_function(L):
+    syms = L.header_symbols(L.HEADER3)
+    assert len(syms) >= 10 and all(s.startswith("fdtd3d_") for s in syms)
+    out = subprocess.run(["nm", "-D", "--defined-only", SO], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    assert not [s for s in syms if s not in exported]
+
+
+def test_3d_valid_descriptor_plans(L):
+    rc, n, _ = _code3(_p3())
+    assert rc == 0 and n > 0
+    rc64, n64, _ = _code3(_p3(), precision="f64")
+    assert rc64 == 0 and n64 > n          # FP64 fields take more room
+
+
+def test_3d_plasma_support_is_compact(L):
+    """Only rows holding plasma carry J and coefficients: a one-row plasma
+    costs far less than a full one."""
+    p = _p3()
+    w_one = np.zeros_like(p.wp2)
+    w_one[0, 6, 6, 3:9] = 1e21
+    w_all = np.full_like(p.wp2, 1e21)
+    _, n_vac, _ = _code3(p)
+    _, n_one, _ = _code3(p.copy(wp2=w_one))
+    _, n_all, _ = _code3(p.copy(wp2=w_all))
+    assert n_one - n_vac < 4096
+    assert n_all - n_vac >= 0.95 * 12 * 12 * 16 * (3 * 4 + 6 * 8)   # J (f32) + wp2, nu (f64)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p: p.copy(dt=p.dt * 1.2), -2),                       # c dt/d above 1/sqrt(3)
+    (lambda p: p.copy(b0=0), -1),
+    (lambda p: p.copy(b1=12), -1),                                # past the walled x face
+    (lambda p: p.copy(cpml=8), -1),
+    (lambda p: p.copy(points=np.array([(6, 0, 0, 0)], np.int32)), -1),
+    (lambda p: p.copy(points=np.array([(0, 12, 0, 0)], np.int32)), -1),
+    (lambda p: p.copy(source="planar", src_comp=2), -1),
+    (lambda p: p.copy(source="planar", src_k=16), -1),
+    (lambda p: p.copy(wp2=np.where(np.arange(16) == 3, -1.0, p.wp2)), -1),
+    (lambda p: p.copy(nu=np.where(np.arange(16) == 3, np.nan, p.nu)), -1),
+])
+def test_3d_invalid_descriptors_rejected(L, mutate, code):
+    rc, _, _ = _code3(mutate(_p3()))
+    assert rc == code
+    assert len(L.lib().fdtd3d_last_error()) > 0
+
+
+def test_3d_struct_size_and_slots(L):
+    rc, _, d = _code3(_p3(), sample_slots=33)
+    assert rc == -1
+    d.sample_slots = 0
+    d.struct_size -= 8
+    n = ctypes.c_size_t()
+    assert L.lib().fdtd3d_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == -1
+
+
+def test_3d_null_handle(L):
+    lib = L.lib()
+    assert lib.fdtd3d_step(None, 1) == -1
+    assert lib.fdtd3d_destroy(None) == 0
