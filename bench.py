@@ -147,6 +147,7 @@ def adjoint_leg(precision="f32"):
         xv = hv.spectra()[0, 0].reshape(1, -1)
     h = FdtdPlasma(p, precision=precision, exec="tiled", checkpoint=T)
     h.run(T)
+    h.grad_r2(T, xv)                 # first call captures the reverse sweep's graph
     h.synchronize()
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record(h.stream)

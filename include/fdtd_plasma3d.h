@@ -55,7 +55,8 @@ enum { FDTD3D_SRC_NONE = 0, FDTD3D_SRC_PLANAR = 1, FDTD3D_SRC_TFSF = 2 };
 /* How a time step is executed (identical bits either way):
  * SPLIT: an H pass and an E/J pass over the grid, fields updated in place;
  * FUSED: one pass (tiles marching along x with E staged in LDS), E, H and the
- *        CPML auxiliaries ping-ponged between two copies.  AUTO = FUSED. */
+ *        CPML auxiliaries ping-ponged between two copies.  AUTO = SPLIT (the
+ *        faster of the two on MI355X at present). */
 enum { FDTD3D_EXEC_AUTO = 0, FDTD3D_EXEC_SPLIT = 1, FDTD3D_EXEC_FUSED = 2 };
 
 /* Field selectors of get/set_fields: E, H components, then the currents. */

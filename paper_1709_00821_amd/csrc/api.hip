@@ -109,6 +109,10 @@ struct fdtd_plasma {
     int64_t win_base = 0;     // samples of m in (win_base, win_base + SB] are buffered
 
     std::map<int64_t, hipGraphExec_t> graphs;
+    // captured reverse sweeps, keyed by nsteps * 64 + probe: the sweep is
+    // ~3 launches per step on small grids, so replaying it from a graph
+    // removes most of the per-launch host cost
+    std::map<int64_t, hipGraphExec_t> adj_graphs;
     bool poisoned = false;
 
     // side stream for the few CPML-touching tiles, which otherwise add their
@@ -998,8 +1002,30 @@ int fdtd_plasma_grad_r2(fdtd_plasma *h, int64_t nsteps, int32_t probe, const dou
     launch_adj_prepare(h->d_Xtmp, h->batch, h->P, h->F, probe, h->d_xref, h->d_G, h->d_loss, h->stream);
     launch_adj_source(h->d_freqs, h->F, h->d.dt, h->d_G, h->batch, nsteps, h->d_gsrc, h->stream);
     launch_adj_coef(h->grids(), h->nodes, h->d_tab, h->stream);
-    rc = h->esize == 8 ? reverse_sweep<double>(h, nsteps, probe) : reverse_sweep<float>(h, nsteps, probe);
-    if (rc) return rc;
+    if (h->stream == nullptr) {
+        // the legacy null stream cannot be captured: launch eagerly
+        rc = h->esize == 8 ? reverse_sweep<double>(h, nsteps, probe) : reverse_sweep<float>(h, nsteps, probe);
+        if (rc) return rc;
+    } else {
+        const int64_t key = nsteps * 64 + probe;
+        auto it = h->adj_graphs.find(key);
+        if (it == h->adj_graphs.end()) {
+            HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            rc = h->esize == 8 ? reverse_sweep<double>(h, nsteps, probe) : reverse_sweep<float>(h, nsteps, probe);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(h->stream, &graph);
+            if (rc || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc ? rc : fail(FDTD_E_DEVICE, "adjoint graph capture failed: %s", hipGetErrorString(e));
+            }
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(FDTD_E_DEVICE, "adjoint graph instantiate failed: %s", hipGetErrorString(e));
+            it = h->adj_graphs.emplace(key, exec).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    }
     // the sweep works in the segment buffer: fields, spectra and checkpoints
     // still hold the forward run, so another loss can reuse it
     std::vector<double> gpad(h->nodes);
@@ -1068,6 +1094,7 @@ int fdtd_plasma_destroy(fdtd_plasma *h)
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : h->adj_graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
     delete h;
     return FDTD_OK;

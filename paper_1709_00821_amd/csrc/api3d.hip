@@ -185,7 +185,7 @@ int plan3(const fdtd3d_desc *d, Plan3 &pl, bool keep_tables)
         pl.slab[1] = d->periodic_y ? 0 : d->nx * P2 * d->nz;
         pl.slab[2] = d->nx * d->ny * P2;
     }
-    pl.exec = d->exec == FDTD3D_EXEC_SPLIT ? FDTD3D_EXEC_SPLIT : FDTD3D_EXEC_FUSED;
+    pl.exec = d->exec == FDTD3D_EXEC_FUSED ? FDTD3D_EXEC_FUSED : FDTD3D_EXEC_SPLIT;
     // the fused kernel's x chunks: enough workgroups to fill 256 CUs several
     // times over, chunks long enough that the one-plane lead-in stays small
     pl.ni = 32;
