@@ -88,6 +88,10 @@ typedef struct {
     int32_t sample_slots;      /* samples buffered per point between DFT flushes;
                                 * 0 = 32, else 1..32 */
     int32_t exec;              /* FDTD3D_EXEC_* */
+    int32_t x_planes;          /* x-planes each thread of the split kernels walks (1..16,
+                                * default 4), or each fused-kernel workgroup (2..128,
+                                * default 32); 0 = default */
+    int32_t reserved;
     void *stream;              /* hipStream_t to launch on (NULL: the legacy null stream,
                                 * which also disables graph capture in fdtd3d_run) */
 } fdtd3d_desc;

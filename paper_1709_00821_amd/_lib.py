@@ -85,6 +85,8 @@ class Desc3(ctypes.Structure):
         ("freqs_hz", ctypes.c_void_p),
         ("sample_slots", ctypes.c_int32),
         ("exec", ctypes.c_int32),
+        ("x_planes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

@@ -74,6 +74,7 @@ struct Plan3 {
     // workspace offsets; [2]: the two copies of the ping-ponged state
     int64_t oE[2][3], oH[2][3], oJ[3], oW[3], oNu[3], oSpan, oOff, oPsiH[2][3][2], oPsiE[2][3][2], oTab,
         oEi[2], oHi, oPts, oFreq, oX, oXt, oBuf, oTw;
+    int64_t oCA[3], oCJ[3], oCH[3], oCa[3], oCb1[3], oCb2[3];   // coefficient tables of the support
     int64_t total = 0;
 };
 
@@ -131,6 +132,9 @@ int validate3(const fdtd3d_desc *d)
         return fail3(FDTD_E_INVALID, "sample_slots %d (0..%d)", d->sample_slots, kSlotsMax);
     if (d->exec < FDTD3D_EXEC_AUTO || d->exec > FDTD3D_EXEC_FUSED)
         return fail3(FDTD_E_INVALID, "exec %d", d->exec);
+    const bool fused = d->exec == FDTD3D_EXEC_FUSED;
+    if (d->x_planes != 0 && (fused ? (d->x_planes < 2 || d->x_planes > 128) : (d->x_planes < 1 || d->x_planes > 16)))
+        return fail3(FDTD_E_INVALID, "x_planes %d out of range for this executor", d->x_planes);
     return FDTD_OK;
 }
 
@@ -187,8 +191,9 @@ int plan3(const fdtd3d_desc *d, Plan3 &pl, bool keep_tables)
     }
     pl.exec = d->exec == FDTD3D_EXEC_FUSED ? FDTD3D_EXEC_FUSED : FDTD3D_EXEC_SPLIT;
     // the fused kernel's x chunks: enough workgroups to fill 256 CUs several
-    // times over, chunks long enough that the one-plane lead-in stays small
-    pl.ni = 32;
+    // times over, chunks long enough that the one-plane lead-in stays small;
+    // the split kernels' planes per thread
+    pl.ni = d->x_planes ? d->x_planes : (pl.exec == FDTD3D_EXEC_FUSED ? 32 : 4);
     Layout3 L;
     const int es = pl.esize;
     const int copies = pl.exec == FDTD3D_EXEC_FUSED ? 2 : 1;
@@ -212,6 +217,14 @@ int plan3(const fdtd3d_desc *d, Plan3 &pl, bool keep_tables)
     // (above: the state that a reset zeroes; below: tables and scratch)
     for (int c = 0; c < 3; ++c) pl.oW[c] = L.take(S * 8);
     for (int c = 0; c < 3; ++c) pl.oNu[c] = L.take(S * 8);
+    for (int c = 0; c < 3; ++c) {
+        pl.oCA[c] = L.take(S * es);
+        pl.oCJ[c] = L.take(S * es);
+        pl.oCH[c] = L.take(S * es);
+        pl.oCa[c] = L.take(S * 8);
+        pl.oCb1[c] = L.take(S * 8);
+        pl.oCb2[c] = L.take(S * 8);
+    }
     pl.oSpan = L.take(pl.rows * 8);
     pl.oOff = L.take(pl.rows * 8);
     pl.oTab = L.take(3 * 4 * std::max<int64_t>(P2, 1) * es);
@@ -305,8 +318,12 @@ Plasma3<T> plasma_of(const fdtd3d *h)
     p.off = h->at<int64_t>(h->pl.oOff);
     for (int c = 0; c < 3; ++c) {
         p.J[c] = h->at<T>(h->pl.oJ[c]);
-        p.wp2[c] = h->at<double>(h->pl.oW[c]);
-        p.nu[c] = h->at<double>(h->pl.oNu[c]);
+        p.eA[c] = h->at<T>(h->pl.oCA[c]);
+        p.eJ[c] = h->at<T>(h->pl.oCJ[c]);
+        p.eH[c] = h->at<T>(h->pl.oCH[c]);
+        p.ca[c] = h->at<double>(h->pl.oCa[c]);
+        p.cb1[c] = h->at<double>(h->pl.oCb1[c]);
+        p.cb2[c] = h->at<double>(h->pl.oCb2[c]);
     }
     return p;
 }
@@ -471,6 +488,7 @@ int fdtd3d_create(const fdtd3d_desc *desc, void *workspace, size_t bytes, fdtd3d
     g.ny = d.ny;
     g.nz = d.nz;
     g.kb = (d.nz + 63) / 64;
+    g.np = pl.exec == FDTD3D_EXEC_FUSED ? 1 : pl.ni;
     g.jb = (d.ny + 3) / 4;
     g.px = d.periodic_x;
     g.py = d.periodic_y;
@@ -549,6 +567,29 @@ int fdtd3d_create(const fdtd3d_desc *desc, void *workspace, size_t bytes, fdtd3d
         e = hipMemcpy(h->ws + pl.oFreq, h->freqs.data(), pl.F * 8, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return undo(fail3(FDTD_E_DEVICE, "create copies failed: %s", hipGetErrorString(e)));
+    // coefficient tables of the plasma support (a0), built on the device
+    if (e == hipSuccess && pl.S > 0) {
+        const double *w[3], *n[3];
+        double *ca[3], *cb1[3], *cb2[3];
+        void *eA[3], *eJ[3], *eH[3];
+        for (int c = 0; c < 3; ++c) {
+            w[c] = h->at<double>(pl.oW[c]);
+            n[c] = h->at<double>(pl.oNu[c]);
+            ca[c] = h->at<double>(pl.oCa[c]);
+            cb1[c] = h->at<double>(pl.oCb1[c]);
+            cb2[c] = h->at<double>(pl.oCb2[c]);
+            eA[c] = h->ws + pl.oCA[c];
+            eJ[c] = h->ws + pl.oCJ[c];
+            eH[c] = h->ws + pl.oCH[c];
+        }
+        if (pl.esize == 8)
+            launch_coef3d<double>(w, n, pl.S, d.dt, d.d, (double *const *)eA, (double *const *)eJ,
+                                  (double *const *)eH, ca, cb1, cb2, h->stream);
+        else
+            launch_coef3d<float>(w, n, pl.S, d.dt, d.d, (float *const *)eA, (float *const *)eJ,
+                                 (float *const *)eH, ca, cb1, cb2, h->stream);
+        e = hipGetLastError();
+    }
     // the host pointers of the caller are not kept
     for (int c = 0; c < 3; ++c) h->d.wp2[c] = h->d.nu[c] = nullptr;
     h->d.points = nullptr;

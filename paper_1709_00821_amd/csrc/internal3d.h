@@ -20,7 +20,7 @@ struct Geo3 {
     int32_t P;                    // CPML cells per walled end (0: none)
     int32_t src;                  // 0 none, 1 planar, 2 TF/SF
     int32_t src_comp;
-    int32_t pad;
+    int32_t np;                   // x-planes per thread (split kernels)
     int64_t src_k;
     int64_t b0, b1;               // TF box
     int64_t xlo, xhi, ylo, yhi;   // Ex/Hy index ranges of the TF box (i: [xlo,xhi), j: [ylo,yhi))
@@ -36,15 +36,27 @@ struct Fields3 {
 };
 
 // Plasma support: per row (i, j) the span [k0, k1) of nodes with a current;
-// the row's nodes are stored compactly from off[row].
+// the row's nodes are stored compactly from off[row].  The per-node
+// coefficients of each E component are built once per create (k_coef3d)
+// into compact tables: the E-update triple in the storage precision (FP64:
+// CA, CJ, CH; FP32: CA - 1, CJ, CH) and the exponential-integrator triple
+// a, b1, b2 of the J update in FP64.
 template <typename T>
 struct Plasma3 {
     const int2 *span;             // [nx*ny] (k0, k1); k0 == k1: no plasma in the row
     const int64_t *off;           // [nx*ny]
     T *J[3];                      // compact [S]
-    const double *wp2[3];         // compact [S]
-    const double *nu[3];          // compact [S]
+    const T *eA[3], *eJ[3], *eH[3];          // compact [S]
+    const double *ca[3], *cb1[3], *cb2[3];   // compact [S]
 };
+
+// Build the compact coefficient tables from wp2, nu (compact, FP64).
+template <typename T>
+void launch_coef3d(const double *const wp2[3], const double *const nu[3], int64_t S, double dt, double d,
+                   T *const eA[3], T *const eJ[3], T *const eH[3], double *const ca[3], double *const cb1[3],
+                   double *const cb2[3], hipStream_t st);
+
+
 
 // CPML auxiliaries, one slab pair per walled axis.  Slab index s in [0, 2P):
 // s < P is node s, s >= P is node n - 2P + s.  Slab arrays:

@@ -32,21 +32,25 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t bid, int64_t nblk)
     return x * q + (x < r ? x : r) + j;
 }
 
-struct Cell {
-    int64_t i, j, k, p;
+// Cells of a split-kernel workgroup: 64 consecutive k (one wave) x 4 rows j
+// x a run of g.np planes i that each thread walks.  i and j are the
+// same for the whole wave (kept in scalar registers).
+struct Col {
+    int64_t i0, i1, j, k;
     bool ok;
 };
 
-__device__ __forceinline__ Cell cell_of(const Geo3 &g)
+__device__ __forceinline__ Col col_of(const Geo3 &g)
 {
-    Cell c;
+    Col c;
     const int64_t bid = xcd_chunk(blockIdx.x, gridDim.x);
     const int64_t kq = bid % g.kb, r = bid / g.kb;
-    c.j = (r % g.jb) * 4 + (threadIdx.x >> 6);
-    c.i = r / g.jb;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    c.j = (r % g.jb) * 4 + w;
+    c.i0 = (r / g.jb) * g.np;
+    c.i1 = c.i0 + g.np < g.nx ? c.i0 + g.np : g.nx;
     c.k = kq * 64 + (threadIdx.x & 63);
     c.ok = c.j < g.ny && c.k < g.nz;
-    c.p = (c.i * g.ny + c.j) * g.nz + c.k;
     return c;
 }
 
@@ -132,20 +136,43 @@ __device__ __forceinline__ void h_cell(const Geo3 &g, const Cpml3<T> &c, const d
     }
 }
 
-// Plasma node coefficients of one component (FP64 CH kept for the TF/SF term).
 template <typename T>
-__device__ __forceinline__ NodeCoef<T> coef3(double wp2, double nu, double dt, double d, double &CH)
+__device__ __forceinline__ NodeCoef<T> coef_at(const Plasma3<T> &pl, int c, int64_t q)
 {
-    const Coef c = node_coef(wp2, nu, dt, d, 0);
     NodeCoef<T> r;
-    r.eA = sizeof(T) == 8 ? (T)c.CA : (T)c.CAm1;
-    r.eJ = (T)c.CJ;
-    r.eH = (T)c.CH;
-    r.a = c.a;
-    r.b1 = c.b1;
-    r.b2 = c.b2;
-    CH = c.CH;
+    r.eA = pl.eA[c][q];
+    r.eJ = pl.eJ[c][q];
+    r.eH = pl.eH[c][q];
+    r.a = pl.ca[c][q];
+    r.b1 = pl.cb1[c][q];
+    r.b2 = pl.cb2[c][q];
     return r;
+}
+
+// Coefficient tables of the plasma support (once per create): node_coef of
+// physics.h per node and component.
+template <typename T>
+__global__ void k_coef3d(const double *w0, const double *w1, const double *w2, const double *n0,
+                         const double *n1, const double *n2, int64_t S, double dt, double d, T *eA0, T *eA1,
+                         T *eA2, T *eJ0, T *eJ1, T *eJ2, T *eH0, T *eH1, T *eH2, double *a0, double *a1,
+                         double *a2, double *b10, double *b11, double *b12, double *b20, double *b21,
+                         double *b22)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= S) return;
+    const double *w[3] = {w0, w1, w2}, *n[3] = {n0, n1, n2};
+    T *eA[3] = {eA0, eA1, eA2}, *eJ[3] = {eJ0, eJ1, eJ2}, *eH[3] = {eH0, eH1, eH2};
+    double *a[3] = {a0, a1, a2}, *b1[3] = {b10, b11, b12}, *b2[3] = {b20, b21, b22};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const NodeCoef<T> r = node_coef_t<T>(w[c][q], n[c][q], dt, d, 0);
+        eA[c][q] = r.eA;
+        eJ[c][q] = r.eJ;
+        eH[c][q] = r.eH;
+        a[c][q] = r.a;
+        b1[c][q] = r.b1;
+        b2[c][q] = r.b2;
+    }
 }
 
 // E update with the 3D curl sign: E_new = CA E - CJ J + CH curl.
@@ -218,10 +245,11 @@ __device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, cons
         e2 = fmat(ce, curl2, eo2);
     } else {
         cq = pl.off[row] + (k - sp.x);
-        double CH1;
-        c0 = coef3<T>(pl.wp2[0][cq], pl.nu[0][cq], g.dt, g.d, CH0);
-        c1 = coef3<T>(pl.wp2[1][cq], pl.nu[1][cq], g.dt, g.d, CH1);
-        c2 = coef3<T>(pl.wp2[2][cq], pl.nu[2][cq], g.dt, g.d, CH2);
+        c0 = coef_at(pl, 0, cq);
+        c1 = coef_at(pl, 1, cq);
+        c2 = coef_at(pl, 2, cq);
+        CH0 = (double)c0.eH;
+        CH2 = (double)c2.eH;
         e0 = e_plasma3(eo0, pl.J[0][cq], curl0, c0);
         e1 = e_plasma3(eo1, pl.J[1][cq], curl1, c1);
         e2 = e_plasma3(eo2, pl.J[2][cq], curl2, c2);
@@ -253,52 +281,76 @@ __device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, cons
 }
 
 // ---- two-kernel step (in place) --------------------------------------------
+//
+// Each thread walks g.np planes along x for one (j, k): the x
+// neighbour it loads for plane i is its own value at plane i+1 (H kernel) or
+// was its own value at plane i-1 (E kernel), so it is read once.
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_h3d(Geo3 g, Fields3<T> f, Cpml3<T> c, const double *Einc)
 {
-    const Cell q = cell_of(g);
+    const Col q = col_of(g);
     if (!q.ok) return;
-    const int64_t i = q.i, j = q.j, k = q.k, p = q.p;
+    const int64_t j = q.j, k = q.k;
     const int64_t sI = g.ny * g.nz, sJ = g.nz;
     const T *Ex = f.E[0], *Ey = f.E[1], *Ez = f.E[2];
-    // +1 neighbours: periodic wrap, or zero beyond a wall (loads stay in bounds)
-    const bool hasi = g.px || i + 1 < g.nx, hasj = g.py || j + 1 < g.ny, hask = k + 1 < g.nz;
-    const int64_t ip = i + 1 < g.nx ? p + sI : p - i * sI;
-    const int64_t jp = j + 1 < g.ny ? p + sJ : p - j * sJ;
-    const int64_t kp = hask ? p + 1 : p;
+    const bool hasj = g.py || j + 1 < g.ny, hask = k + 1 < g.nz;
+    const int64_t dj = j + 1 < g.ny ? sJ : -j * sJ;       // +1 row, periodic wrap
+    const int64_t dk = hask ? 1 : 0;
     const T zero = (T)0;
-    const T ez_j = Ez[jp], ey_k = Ey[kp], ex_k = Ex[kp], ez_i = Ez[ip], ey_i = Ey[ip], ex_j = Ex[jp];
-    T hx = f.H[0][p], hy = f.H[1][p], hz = f.H[2][p];
-    h_cell<T>(g, c, Einc, i, j, k, Ex[p], Ey[p], Ez[p], hasj ? ex_j : zero, hask ? ex_k : zero,
-              hasi ? ey_i : zero, hask ? ey_k : zero, hasi ? ez_i : zero, hasj ? ez_j : zero, hx, hy, hz, true);
-    f.H[0][p] = hx;
-    f.H[1][p] = hy;
-    f.H[2][p] = hz;
+    int64_t p = (q.i0 * g.ny + j) * g.nz + k;
+    T ex = Ex[p], ey = Ey[p], ez = Ez[p];
+    for (int64_t i = q.i0; i < q.i1; ++i, p += sI) {
+        // plane i+1: periodic wrap to plane 0, or zero beyond the wall
+        const bool hasi = g.px || i + 1 < g.nx;
+        const int64_t pn = i + 1 < g.nx ? p + sI : p - i * sI;
+        const T ex1 = Ex[pn], ey1 = Ey[pn], ez1 = Ez[pn];
+        const T ez_j = Ez[p + dj], ex_j = Ex[p + dj], ey_k = Ey[p + dk], ex_k = Ex[p + dk];
+        T hx = f.H[0][p], hy = f.H[1][p], hz = f.H[2][p];
+        h_cell<T>(g, c, Einc, i, j, k, ex, ey, ez, hasj ? ex_j : zero, hask ? ex_k : zero,
+                  hasi ? ey1 : zero, hask ? ey_k : zero, hasi ? ez1 : zero, hasj ? ez_j : zero, hx, hy, hz, true);
+        f.H[0][p] = hx;
+        f.H[1][p] = hy;
+        f.H[2][p] = hz;
+        ex = ex1;
+        ey = ey1;
+        ez = ez1;
+    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_e3d(Geo3 g, Fields3<T> f, Plasma3<T> pl, Cpml3<T> c,
                                              const double *Hinc, double sval)
 {
-    const Cell q = cell_of(g);
+    const Col q = col_of(g);
     if (!q.ok) return;
-    const int64_t i = q.i, j = q.j, k = q.k, p = q.p;
+    const int64_t j = q.j, k = q.k;
     const int64_t sI = g.ny * g.nz, sJ = g.nz;
     const T *Hx = f.H[0], *Hy = f.H[1], *Hz = f.H[2];
-    // -1 neighbours: periodic wrap, or zero beyond a wall
-    const bool hasi = g.px || i > 0, hasj = g.py || j > 0, hask = k > 0;
-    const int64_t im = i > 0 ? p - sI : p + (g.nx - 1) * sI;
-    const int64_t jm = j > 0 ? p - sJ : p + (g.ny - 1) * sJ;
-    const int64_t km = hask ? p - 1 : p;
+    const bool hasj = g.py || j > 0, hask = k > 0;
+    const int64_t dj = j > 0 ? -sJ : (g.ny - 1) * sJ;       // -1 row, periodic wrap
+    const int64_t dk = hask ? -1 : 0;
     const T zero = (T)0;
-    const T hz_j = Hz[jm], hy_k = Hy[km], hx_k = Hx[km], hz_i = Hz[im], hy_i = Hy[im], hx_j = Hx[jm];
-    T e0 = f.E[0][p], e1 = f.E[1][p], e2 = f.E[2][p];
-    e_cell<T>(g, pl, c, Hinc, sval, i, j, k, Hx[p], Hy[p], Hz[p], hasj ? hx_j : zero, hask ? hx_k : zero,
-              hasi ? hy_i : zero, hask ? hy_k : zero, hasi ? hz_i : zero, hasj ? hz_j : zero, e0, e1, e2);
-    f.E[0][p] = e0;
-    f.E[1][p] = e1;
-    f.E[2][p] = e2;
+    int64_t p = (q.i0 * g.ny + j) * g.nz + k;
+    // plane i0-1: periodic wrap to plane nx-1, or zero beyond the wall
+    T hy_i = zero, hz_i = zero;
+    if (q.i0 > 0 || g.px) {
+        const int64_t pm = q.i0 > 0 ? p - sI : p + (g.nx - 1) * sI;
+        hy_i = Hy[pm];
+        hz_i = Hz[pm];
+    }
+    for (int64_t i = q.i0; i < q.i1; ++i, p += sI) {
+        const T hx = Hx[p], hy = Hy[p], hz = Hz[p];
+        const T hz_j = Hz[p + dj], hx_j = Hx[p + dj], hy_k = Hy[p + dk], hx_k = Hx[p + dk];
+        T e0 = f.E[0][p], e1 = f.E[1][p], e2 = f.E[2][p];
+        e_cell<T>(g, pl, c, Hinc, sval, i, j, k, hx, hy, hz, hasj ? hx_j : zero, hask ? hx_k : zero, hy_i,
+                  hask ? hy_k : zero, hz_i, hasj ? hz_j : zero, e0, e1, e2);
+        f.E[0][p] = e0;
+        f.E[1][p] = e1;
+        f.E[2][p] = e2;
+        hy_i = hy;
+        hz_i = hz;
+    }
 }
 
 // ---- fused step ---------------------------------------------------------------
@@ -456,14 +508,18 @@ __global__ void k_tw3d(const double *freqs, int F, double dt, int64_t m0, int cn
     tw[t] = make_double2(re, im);
 }
 
-// X[f][q] += sum_s v_s tw_s,f, slots in order; one thread per point.
+// X[f][q] += sum_s v_s tw_s,f, slots in order; one thread per point.  The
+// twiddle indices are wave-uniform, so both the E and the H twiddle are read
+// as scalars and each lane picks its own.
 template <typename T>
-__global__ __launch_bounds__(256) void k_flush3d(const T *buf, int cnt, int64_t npts, const int64_t *pts,
-                                                 int64_t N, int F, const double2 *tw, double2 *X)
+__global__ __launch_bounds__(256) void k_flush3d(const T *__restrict__ buf, int cnt, int64_t npts,
+                                                 const int64_t *__restrict__ pts, int64_t N, int F,
+                                                 const double2 *__restrict__ tw, double2 *__restrict__ X)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npts) return;
-    const double2 *t = tw + (pts[q] >= 3 * N ? (int64_t)cnt * F : 0);
+    const bool isH = pts[q] >= 3 * N;
+    const double2 *tH = tw + (int64_t)cnt * F;
     double v[kSlotsMax];
 #pragma unroll
     for (int s = 0; s < kSlotsMax; ++s) v[s] = s < cnt ? (double)buf[(int64_t)s * npts + q] : 0.0;
@@ -472,9 +528,10 @@ __global__ __launch_bounds__(256) void k_flush3d(const T *buf, int cnt, int64_t 
 #pragma unroll
         for (int s = 0; s < kSlotsMax; ++s) {
             if (s < cnt) {
-                const double2 w = t[(int64_t)s * F + fi];
-                x.x = __builtin_fma(v[s], w.x, x.x);
-                x.y = __builtin_fma(v[s], w.y, x.y);
+                const double2 we = tw[(int64_t)s * F + fi], wh = tH[(int64_t)s * F + fi];
+                const double wr = isH ? wh.x : we.x, wi = isH ? wh.y : we.y;
+                x.x = __builtin_fma(v[s], wr, x.x);
+                x.y = __builtin_fma(v[s], wi, x.y);
             }
         }
         X[(int64_t)fi * npts + q] = x;
@@ -497,7 +554,21 @@ __global__ void k_copy3d(uint4 *dst, const uint4 *src, int64_t n16)
 
 // ---- launchers ----------------------------------------------------------------
 
-static dim3 grid3(const Geo3 &g) { return dim3((unsigned)(g.kb * g.jb * g.nx)); }
+static dim3 grid3(const Geo3 &g)
+{
+    return dim3((unsigned)(g.kb * g.jb * ((g.nx + g.np - 1) / g.np)));
+}
+
+template <typename T>
+void launch_coef3d(const double *const w[3], const double *const n[3], int64_t S, double dt, double d,
+                   T *const eA[3], T *const eJ[3], T *const eH[3], double *const a[3], double *const b1[3],
+                   double *const b2[3], hipStream_t st)
+{
+    if (S <= 0) return;
+    hipLaunchKernelGGL(k_coef3d<T>, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st, w[0], w[1], w[2], n[0],
+                       n[1], n[2], S, dt, d, eA[0], eA[1], eA[2], eJ[0], eJ[1], eJ[2], eH[0], eH[1], eH[2], a[0],
+                       a[1], a[2], b1[0], b1[1], b1[2], b2[0], b2[1], b2[2]);
+}
 
 template <typename T>
 void launch_h3d(const Geo3 &g, const Fields3<T> &f, const Cpml3<T> &c, const double *Einc, hipStream_t st)
@@ -581,7 +652,10 @@ void launch_copy3d(void *dst, const void *src, int64_t bytes, hipStream_t st)
     template void launch_sample3d<T>(const Fields3<T> &, int64_t, const int64_t *, int64_t, T *,         \
                                      hipStream_t);                                                        \
     template void launch_flush3d<T>(const T *, int, int64_t, const int64_t *, int64_t, int,             \
-                                    const double2 *, double2 *, hipStream_t);
+                                    const double2 *, double2 *, hipStream_t);                             \
+    template void launch_coef3d<T>(const double *const[3], const double *const[3], int64_t, double,     \
+                                   double, T *const[3], T *const[3], T *const[3], double *const[3],      \
+                                   double *const[3], double *const[3], hipStream_t);
 INST3(float)
 INST3(double)
 #undef INST3

@@ -14,7 +14,7 @@ from .workloads import Problem3D
 
 
 def make_desc3(p: Problem3D, precision: str = "f32", sample_slots: int = 0, stream_handle: int = 0,
-               exec: str = "auto"):
+               exec: str = "auto", x_planes: int = 0):
     """The C descriptor of a 3D problem; returns (desc, arrays it points into)."""
     wp2 = [np.ascontiguousarray(p.wp2[c], np.float64) for c in range(3)]
     if p.nu.ndim == 3:
@@ -42,6 +42,7 @@ def make_desc3(p: Problem3D, precision: str = "f32", sample_slots: int = 0, stre
     d.freqs_hz = freqs.ctypes.data if len(freqs) else None
     d.sample_slots = sample_slots
     d.exec = L.EXEC3[exec]
+    d.x_planes = x_planes
     d.stream = stream_handle or None
     return d, [wp2, nu, pts, freqs]
 
@@ -56,14 +57,14 @@ class FdtdPlasma3D:
     """One 3D Yee-RKETD grid."""
 
     def __init__(self, problem: Problem3D, precision: str = "f32", sample_slots: int = 0,
-                 exec: str = "auto", stream: Optional[torch.cuda.Stream] = None,
+                 exec: str = "auto", x_planes: int = 0, stream: Optional[torch.cuda.Stream] = None,
                  device: Union[int, str, torch.device] = "cuda"):
         self.problem = problem
         self.precision = precision
         self.dtype = np.float64 if precision == "f64" else np.float32
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        d, keep = make_desc3(problem, precision, sample_slots, self.stream.cuda_stream, exec)
+        d, keep = make_desc3(problem, precision, sample_slots, self.stream.cuda_stream, exec, x_planes)
         self.desc = d
         self.workspace_bytes = workspace_bytes3(d)
         with torch.cuda.stream(self.stream):
