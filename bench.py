@@ -322,6 +322,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--only", choices=["c3", "batched", "adjoint", "c1"],
+                    help="run just this leg and print its JSON (profiling runs)")
+    ap.add_argument("--c3-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -345,6 +348,11 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: copy calibration: hipMemcpy of {nbytes} bytes (rc {rc})")
         del x, y
+    if args.only:
+        leg = {"c3": lambda: c3_leg(T=args.c3_steps), "batched": batched_leg, "adjoint": adjoint_leg,
+               "c1": c1_leg}[args.only]
+        print(json.dumps({args.only: leg()}), flush=True)
+        return
     from paper_1709_00821_amd import workloads as W
     from paper_1709_00821_amd import tune as TU
 
