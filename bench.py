@@ -130,7 +130,7 @@ def batched_leg(precision="f32", n_slabs=4096, T=8000, reps=2):
     log(f"bench: batched {n_slabs} slabs ({cells} nodes) x {T} steps: {ms:.2f} ms")
     return {"value": round(cells * T / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
             "ms": round(ms, 3), "slabs": n_slabs, "nodes": cells, "time_steps": T,
-            "precision": precision, "exec": "tiled over the concatenated slabs",
+            "precision": precision, "exec": "auto (tiled over the concatenated slabs)",
             "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"]}
 
 

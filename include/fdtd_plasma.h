@@ -62,8 +62,12 @@ enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 
  *           tiles of tile_cells nodes with halo recompute, ping-pong buffers;
  * RESIDENT: one persistent launch; each workgroup keeps whole grids in
  *           registers for the entire run (short grids, e.g. batches of slabs);
+ * MIXED:    per pass, the grids that fit a workgroup run as RESIDENT bins and
+ *           the longer ones as TILED tiles (Mur or PEC ends; batches of
+ *           uneven slabs);
  * AUTO:     RESIDENT when every grid fits a workgroup, else TILED. */
-enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RESIDENT = 3 };
+enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RESIDENT = 3,
+       FDTD_EXEC_MIXED = 4 };
 
 /* flags */
 #define FDTD_FLAG_CHECKPOINT 0x1   /* run() stores sqrt(T)-spaced checkpoints for the adjoint */

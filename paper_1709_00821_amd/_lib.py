@@ -22,7 +22,7 @@ OK, E_INVALID, E_UNSTABLE, E_WORKSPACE, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPP
     0, -1, -2, -3, -4, -5, -6, -7
 F64, F32 = 0, 1
 BC = {"mur": 0, "cpml": 1, "pec": 2}
-EXEC = {"auto": 0, "step": 1, "tiled": 2, "resident": 3}
+EXEC = {"auto": 0, "step": 1, "tiled": 2, "resident": 3, "mixed": 4}
 FLAG_CHECKPOINT = 0x1
 
 

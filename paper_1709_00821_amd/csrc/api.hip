@@ -139,7 +139,7 @@ struct fdtd_plasma {
         hipEvent_t a, b;
         int64_t units;        // output nodes the launch group advances
     };
-    int64_t class_nodes[3] = {0, 0, 0};   // output nodes per tile class
+    int64_t class_nodes[4] = {0, 0, 0, 0};   // output nodes per tile class; [3]: binned grids
     int64_t real_nodes = 0;
     bool profiling = false;
     std::vector<ProfMark> marks;
@@ -200,7 +200,7 @@ int validate(const fdtd_plasma_desc *d)
         return fail(FDTD_E_INVALID, "precision %d", d->precision);
     if (d->scheme < 0 || d->scheme > 2) return fail(FDTD_E_INVALID, "scheme %d", d->scheme);
     if (d->bc < 0 || d->bc > 2) return fail(FDTD_E_INVALID, "bc %d", d->bc);
-    if (d->exec < 0 || d->exec > 3) return fail(FDTD_E_INVALID, "exec %d", d->exec);
+    if (d->exec < 0 || d->exec > 4) return fail(FDTD_E_INVALID, "exec %d", d->exec);
     if (d->batch < 1) return fail(FDTD_E_INVALID, "batch %lld < 1", (long long)d->batch);
     if (!d->cells || !d->wp2 || !d->nu || !d->src_cell || !d->probe_cells || !d->freqs_hz)
         return fail(FDTD_E_INVALID, "a host array pointer is NULL");
@@ -284,7 +284,8 @@ struct Plan {
 
 // Tile tables for the temporally blocked executor: per grid, outputs of width
 // W = tile - 2 Kh; held span [out_lo - Kh, out_hi + Kh) clipped to the grid.
-void build_tiles(const fdtd_plasma_desc *d, Plan &p)
+// Tiles of every grid, or of the grids skip[] does not mark.
+void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *skip = nullptr)
 {
     const int L = p.tileC * 64;
     const int W = L - 2 * p.Kh;
@@ -292,7 +293,7 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p)
     int64_t o = 0;
     for (int64_t b = 0; b < d->batch; ++b) {
         const int64_t n = d->cells[b];
-        for (int64_t out = 0; out < n; out += W) {
+        for (int64_t out = 0; !(skip && (*skip)[b]) && out < n; out += W) {
             Tile t{};
             t.grid = (int32_t)b;
             t.out_lo = (int32_t)out;
@@ -328,8 +329,10 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p)
 }
 
 // Resident bins: grids packed first-fit-decreasing into workgroups of
-// resWaves waves, each grid on ceil(n / (64 C)) consecutive waves.
-bool build_bins(const fdtd_plasma_desc *d, Plan &p)
+// resWaves waves, each grid on ceil(n / (64 C)) consecutive waves.  With
+// skip_long, grids that do not fit a workgroup are left out (MIXED);
+// otherwise such a grid makes the packing fail.
+bool build_bins(const fdtd_plasma_desc *d, Plan &p, bool skip_long = false)
 {
     const int64_t per_wave = 64LL * p.resC;
     std::vector<std::pair<int64_t, int64_t>> need;  // (waves, grid)
@@ -338,7 +341,10 @@ bool build_bins(const fdtd_plasma_desc *d, Plan &p)
         const int64_t n = d->cells[b];
         shift[b] = ((n - 1) % per_wave == 0) ? 1 : 0;
         const int64_t w = (n + shift[b] + per_wave - 1) / per_wave;
-        if (w > p.resWaves) return false;
+        if (w > p.resWaves) {
+            if (skip_long) continue;
+            return false;
+        }
         need.push_back({w, b});
     }
     std::stable_sort(need.begin(), need.end(),
@@ -400,23 +406,40 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     p.resC = 8;
     p.resWaves = 8;   // 512-thread workgroups keep the FP64 coefficients in registers without spills
     p.exec = d->exec;
-    if (p.exec == FDTD_EXEC_RESIDENT && d->bc == FDTD_BC_CPML)
+    if ((p.exec == FDTD_EXEC_RESIDENT || p.exec == FDTD_EXEC_MIXED) && d->bc == FDTD_BC_CPML)
         return fail(FDTD_E_UNSUPPORTED, "the resident executor has no CPML ends");
     if (p.exec == FDTD_EXEC_AUTO && d->bc == FDTD_BC_CPML) p.exec = FDTD_EXEC_TILED;
-    if (p.exec == FDTD_EXEC_RESIDENT || p.exec == FDTD_EXEC_AUTO) {
-        const bool ok = build_bins(d, p);
-        if (!ok && p.exec == FDTD_EXEC_RESIDENT)
-            return fail(FDTD_E_INVALID, "a grid exceeds %d nodes, the resident limit",
-                        64 * p.resC * p.resWaves);
-        if (!ok) p.exec = FDTD_EXEC_TILED;
-        else p.exec = FDTD_EXEC_RESIDENT;
+    const int64_t res_max = resident_max_nodes(p.resC, p.resWaves);
+    if (p.exec == FDTD_EXEC_AUTO) {
+        Plan q = p;
+        build_bins(d, q, true);
+        int64_t fit = 0;
+        std::vector<char> seen(d->batch, 0);
+        for (auto &s : q.slots)
+            if (s.grid >= 0 && !seen[s.grid]) { seen[s.grid] = 1; ++fit; }
+        // (MIXED is left to explicit requests: on the 4096-slab benchmark batch it
+        // is slower than tiles alone, the bins occupying whole CUs for a window)
+        p.exec = fit == d->batch ? FDTD_EXEC_RESIDENT : FDTD_EXEC_TILED;
     }
-    if (p.exec == FDTD_EXEC_TILED) {
+    if (p.exec == FDTD_EXEC_RESIDENT) {
+        if (!build_bins(d, p))
+            return fail(FDTD_E_INVALID, "a grid exceeds %lld nodes, the resident limit", (long long)res_max);
+    }
+    if (p.exec == FDTD_EXEC_MIXED) {
+        build_bins(d, p, true);
+        if (p.nbins == 0) p.exec = FDTD_EXEC_TILED;      // nothing fits: plain tiles
+    }
+    if (p.exec == FDTD_EXEC_TILED || p.exec == FDTD_EXEC_MIXED) {
         if (p.tileC * 64 <= 2 * p.Kh + 64)
             return fail(FDTD_E_INVALID, "tile of %d nodes too small for halo %d", p.tileC * 64, p.Kh);
-        build_tiles(d, p);
+        // MIXED: tiles only for the grids the bins left out
+        std::vector<char> binned(d->batch, 0);
+        if (p.exec == FDTD_EXEC_MIXED)
+            for (auto &s : p.slots)
+                if (s.grid >= 0) binned[s.grid] = 1;
+        build_tiles(d, p, p.exec == FDTD_EXEC_MIXED ? &binned : nullptr);
     }
-    if (p.exec != FDTD_EXEC_RESIDENT) { p.slots.clear(); p.nbins = 0; }
+    if (p.exec != FDTD_EXEC_RESIDENT && p.exec != FDTD_EXEC_MIXED) { p.slots.clear(); p.nbins = 0; }
 
     // sample window: up to 16384 steps, at most ~256 MiB of samples
     {
@@ -562,10 +585,42 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                     prof_end(h);
                 }
             if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
+        } else if (h->exec == FDTD_EXEC_MIXED) {
+            // bins and tiles hold disjoint grids.  The bins advance the whole
+            // window in one launch (beside the tiles on the side stream, unless
+            // profiling) and write the buffer the tile passes end in.
+            k = std::min<int64_t>(left, room);
+            const int64_t passes = (k + h->Kh - 1) / h->Kh;
+            const int out = h->cur ^ (int)(passes & 1);
+            const bool fork = h->side && !h->profiling;
+            hipStream_t rs = fork ? h->side : h->stream;
+            if (fork) {
+                (void)hipEventRecord(h->ev_fork, h->stream);
+                (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+            }
+            prof_begin(h, "resident", h->class_nodes[3]);
+            launch_resident<T>(g, s, h->cur, out, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k,
+                               h->steps, slot, rs);
+            prof_end(h);
+            if (fork) (void)hipEventRecord(h->ev_join, h->side);
+            int cur = h->cur;
+            for (int64_t done = 0; done < k; done += h->Kh) {
+                const int kk = (int)std::min<int64_t>(h->Kh, k - done);
+                for (int c = 0; c < 3; ++c)
+                    if (h->ntiles[c]) {
+                        prof_begin(h, kTiledNames[c], h->class_nodes[c]);
+                        launch_tiled<T>(g, s, cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC, kk,
+                                        h->steps + done, slot + (int)done, h->stream);
+                        prof_end(h);
+                    }
+                cur ^= 1;
+            }
+            if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
+            h->cur = out ^ 1;          // flipped back below
         } else {
             k = std::min<int64_t>(left, room);
             prof_begin(h, "resident", h->real_nodes);
-            launch_resident<T>(g, s, h->cur, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k,
+            launch_resident<T>(g, s, h->cur, h->cur, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k,
                                h->steps, slot, h->stream);
             prof_end(h);
         }
@@ -648,6 +703,13 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         }
     }
     for (int64_t b = 0; b < desc->batch; ++b) h->real_nodes += desc->cells[b];
+    {
+        std::vector<char> binned(desc->batch, 0);
+        for (auto &sl : p.slots)
+            if (sl.grid >= 0) binned[sl.grid] = 1;
+        for (int64_t b = 0; b < desc->batch; ++b)
+            if (binned[b]) h->class_nodes[3] += desc->cells[b];
+    }
     h->cells.assign(desc->cells, desc->cells + desc->batch);
     h->off = p.off;
     h->src.assign(desc->src_cell, desc->src_cell + desc->batch);
@@ -751,7 +813,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
                                                      : 0.8 * (m + 1.0) / (eta0 * desc->dz);
         launch_cpml_table(h->d_cpml, desc->cpml_cells, m, smax, desc->dt, st);
     }
-    if (h->exec == FDTD_EXEC_TILED && h->ntiles[2] > 0 && h->stream != nullptr) {
+    if (((h->exec == FDTD_EXEC_TILED && h->ntiles[2] > 0) || h->exec == FDTD_EXEC_MIXED) && h->stream != nullptr) {
         // default priority (no priority streams), non-blocking w.r.t. the null stream
         if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -821,7 +883,8 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
             int64_t k = h->exec == FDTD_EXEC_STEP ? 1
                         : h->exec == FDTD_EXEC_TILED ? std::min<int64_t>(std::min<int64_t>(left, room), h->Kh)
                                                      : std::min<int64_t>(left, room);
-            if (h->exec != FDTD_EXEC_RESIDENT) h->cur ^= 1;
+            if (h->exec == FDTD_EXEC_MIXED) h->cur ^= (int)(((k + h->Kh - 1) / h->Kh) & 1);
+            else if (h->exec != FDTD_EXEC_RESIDENT) h->cur ^= 1;
             h->steps += k;
             left -= k;
             if (h->steps - h->win_base == h->SB) h->win_base = h->steps;
@@ -939,13 +1002,9 @@ int reverse_sweep(fdtd_plasma *h, int64_t Tn, int probe)
     for (int64_t j = nseg - 1; j >= 0; --j) {
         const int64_t m0 = j * h->ck_s, m1 = std::min<int64_t>(Tn, m0 + h->ck_s);
         launch_copy(h->d_seg, h->d_ck + j * ck3, ck3, h->stream);
-        for (int64_t i = 0; i < m1 - m0; ++i) {
-            State<T> s{};
-            s.E[0] = segE(i); s.E[1] = segE(i + 1);
-            s.H[0] = segH(i); s.H[1] = segH(i + 1);
-            s.J[0] = segJ(i); s.J[1] = segJ(i + 1);
-            launch_step<T>(gq, s, 0, h->nodes, m0 + i + 1, 0, h->stream);
-        }
+        for (int64_t i = 0; i < m1 - m0; ++i)
+            launch_recompute1d<T>(gq, segE(i), segH(i), segJ(i), segE(i + 1), segH(i + 1), segJ(i + 1), h->nodes,
+                                  m0 + i + 1, h->stream);
         for (int64_t m = m1 - 1; m >= m0; --m) {
             const int64_t i = m - m0;
             const T *lam[3] = {(const T *)h->d_lam[lc][0], (const T *)h->d_lam[lc][1],

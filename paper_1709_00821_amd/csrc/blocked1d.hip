@@ -460,7 +460,7 @@ template void launch_tiled<double>(const Grids &, State<double> &, int, const Ti
 // holds.  Edge values cross waves through LDS: two barriers per step, taken by
 // every wave of the workgroup (idle waves included) so the count matches.
 template <typename T, int C, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, int cur,
+__global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, int cur, int out,
                                                          const ResidentSlot *slots, int nsteps,
                                                          int64_t m0, int slot0)
 {
@@ -507,22 +507,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
         chunk_step<T, C, true, false>(ck, g, role, m0 + st + 1, get_er, get_hl);
         if (active) chunk_probes<T, C>(g, b, k0, wave_lo < 0 ? 0 : wave_lo, wave_hi, ck.E, slot0 + st);
     }
-    if (active) chunk_store<T, C, true, false>(ck, g, s, cur, b, off, n, k0, 0, n);
+    if (active) chunk_store<T, C, true, false>(ck, g, s, out, b, off, n, k0, 0, n);
 }
 
 template <typename T>
-void launch_resident(const Grids &g, State<T> &s, int cur, const ResidentSlot *slots, int64_t nbins,
+void launch_resident(const Grids &g, State<T> &s, int cur, int out, const ResidentSlot *slots, int64_t nbins,
                      int waves_per_wg, int C, int nsteps, int64_t m0, int slot0, hipStream_t st)
 {
     (void)C;
     (void)waves_per_wg;   // 8 waves: 512 threads keep the per-node coefficients in VGPRs
     hipLaunchKernelGGL((k_resident<T, 8, 8>), dim3((unsigned)nbins), dim3(8 * 64), 0, st, g, s,
-                       cur, slots, nsteps, m0, slot0);
+                       cur, out, slots, nsteps, m0, slot0);
 }
 
-template void launch_resident<float>(const Grids &, State<float> &, int, const ResidentSlot *, int64_t,
+template void launch_resident<float>(const Grids &, State<float> &, int, int, const ResidentSlot *, int64_t,
                                      int, int, int, int64_t, int, hipStream_t);
-template void launch_resident<double>(const Grids &, State<double> &, int, const ResidentSlot *,
+template void launch_resident<double>(const Grids &, State<double> &, int, int, const ResidentSlot *,
                                       int64_t, int, int, int, int64_t, int, hipStream_t);
 
 int resident_max_nodes(int C, int waves) { return 64 * C * waves; }

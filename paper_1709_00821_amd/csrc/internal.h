@@ -86,8 +86,10 @@ template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
                   int klass, int C, int nsteps, int64_t m0, int slot0, hipStream_t st);
 
+// Reads buffer cur, writes buffer out (cur itself for a whole-run resident
+// call, the other buffer when bins and tiles share a pass).
 template <typename T>
-void launch_resident(const Grids &g, State<T> &s, int cur, const ResidentSlot *slots,
+void launch_resident(const Grids &g, State<T> &s, int cur, int out, const ResidentSlot *slots,
                      int64_t nbins, int waves_per_wg, int C, int nsteps, int64_t m0,
                      int slot0, hipStream_t st);
 
@@ -112,5 +114,10 @@ void launch_adj_step(const Grids &g, const T *const lam[3], T *const out[3], con
                      const double *gsrc, int64_t T_, int64_t m, int probe, double *grad,
                      hipStream_t st);
 void launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
+// One forward step (Mur/PEC ends, no probes) as a single launch, for the
+// reverse sweep's recompute; same bits as launch_step.
+template <typename T>
+void launch_recompute1d(const Grids &g, const T *E, const T *H, const T *J, T *En, T *Hn, T *Jn, int64_t total,
+                        int64_t m, hipStream_t st);
 
 }  // namespace fdtdp

@@ -131,7 +131,31 @@ def test_exec_modes_bitwise_identical(G, precision):
                 assert np.array_equal(out[ex][1][b][k], out["step"][1][b][k]), (ex, b, k)
 
 
-@pytest.mark.parametrize("ex", EXECS)
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_mixed_executor_bitwise(G, precision):
+    """Uneven batch across the resident limit (4096 nodes): grids that fit run
+    as resident bins, the others as tiles, in the same passes; bit for bit the
+    per-step executor, and the oracle within 1e-12 (FP64)."""
+    rng = np.random.default_rng(23)
+    probs = [W.random_slab(rng, n, n_freqs=6) for n in (37, 513, 4095, 4096, 4097, 5000, 8128)]
+    probs = [q.copy(freqs=probs[0].freqs) for q in probs]
+    T = 300
+    say(f"case mixed executor {precision} grids={[q.n for q in probs]} steps={T}")
+    Xs, Fs = gpu_run(G, probs, T, precision, "step")
+    Xm, Fm = gpu_run(G, probs, T, precision, "mixed")
+    Xa, Fa = gpu_run(G, probs, T, precision, "tiled")
+    assert np.array_equal(Xm, Xs) and np.array_equal(Xa, Xs)
+    for b in range(len(probs)):
+        for k in ("E", "H", "J"):
+            assert np.array_equal(Fm[b][k], Fs[b][k]), (b, k)
+            assert np.array_equal(Fa[b][k], Fs[b][k]), (b, k)
+    if precision == "f64":
+        for b in (0, 4, 6):
+            Xo = oracle.run(probs[b], T)["X"]
+            assert np.max(np.abs(Xm[b] - Xo)) <= 1e-12 * np.max(np.abs(Xo)), b
+
+
+@pytest.mark.parametrize("ex", EXECS + ["mixed"])
 def test_step_composition_bitwise(G, ex):
     p = W.slab_c1(n=700, slab=(300, 380), src=90, probes=(40, 650), n_freqs=12)
     say(f"case step composition exec={ex}")
