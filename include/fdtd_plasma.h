@@ -59,7 +59,8 @@ enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 
 /* How the time loop is executed (results agree bit for bit across modes):
  * STEP:     two launches per time step (H, then E/J/source/ends/probes);
  * TILED:    temporal blocking, steps_per_pass steps per launch on register
- *           tiles of tile_cells nodes with halo recompute, ping-pong buffers;
+ *           tiles of tile_waves waves of tile_cells nodes each, with halo
+ *           recompute at the tile ends, ping-pong buffers;
  * RESIDENT: one persistent launch; each workgroup keeps whole grids in
  *           registers for the entire run (short grids, e.g. batches of slabs);
  * MIXED:    per pass, the grids that fit a workgroup run as RESIDENT bins and
@@ -99,6 +100,10 @@ typedef struct {
     int32_t steps_per_pass;      /* TILED: time steps per launch (halo depth); 0 = default */
     int32_t checkpoint_steps;    /* with FDTD_FLAG_CHECKPOINT: longest run the checkpoint and
                                     adjoint storage is sized for (>= 1) */
+    int32_t tile_waves;          /* TILED: waves per tile (1, 2, 4 or 8; neighbouring waves of a
+                                    tile exchange edge values through LDS every step, so the
+                                    halo is paid once per tile_waves*tile_cells nodes); 0 = default */
+    int32_t reserved;
     void *stream;                /* hipStream_t for every launch and copy; NULL = null stream */
 } fdtd_plasma_desc;
 

@@ -60,6 +60,8 @@ class Desc(ctypes.Structure):
         ("cpml_sigma_max", ctypes.c_double),
         ("steps_per_pass", ctypes.c_int32),
         ("checkpoint_steps", ctypes.c_int32),
+        ("tile_waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

@@ -94,7 +94,7 @@ struct fdtd_plasma {
     Tile *d_tiles = nullptr;
     int64_t ntiles[3] = {0, 0, 0};
     int64_t tile_first[3] = {0, 0, 0};
-    int tileC = 8, Kh = 16;
+    int tileC = 8, Kh = 16, tileW = 1;
 
     // resident executor
     ResidentSlot *d_slots = nullptr;
@@ -256,6 +256,10 @@ int validate(const fdtd_plasma_desc *d)
     if (d->flags & ~FDTD_FLAG_CHECKPOINT) return fail(FDTD_E_INVALID, "unknown flags 0x%x", d->flags);
     if (d->tile_cells != 0 && (d->tile_cells % 256 != 0 || d->tile_cells < 256 || d->tile_cells > 1024))
         return fail(FDTD_E_INVALID, "tile_cells %d: must be 0, 256, 512, 768 or 1024", d->tile_cells);
+    if (d->tile_waves != 0 && d->tile_waves != 1 && d->tile_waves != 2 && d->tile_waves != 4 && d->tile_waves != 8)
+        return fail(FDTD_E_INVALID, "tile_waves %d: must be 0, 1, 2, 4 or 8", d->tile_waves);
+    if (d->tile_waves > 1 && d->tile_cells != 0 && d->tile_cells != 256 && d->tile_cells != 512)
+        return fail(FDTD_E_INVALID, "tile_waves > 1 takes tile_cells 256 or 512");
     if (d->steps_per_pass != 0 && (d->steps_per_pass < 4 || d->steps_per_pass % 4 != 0 ||
                                    d->steps_per_pass > 64))
         return fail(FDTD_E_INVALID, "steps_per_pass %d: must be 0 or a multiple of 4 in [4, 64]",
@@ -279,7 +283,7 @@ struct Plan {
     int64_t ntiles[3] = {0, 0, 0}, tile_first[3] = {0, 0, 0};
     std::vector<ResidentSlot> slots;
     int64_t nbins = 0;
-    int exec = 0, tileC = 8, Kh = 16, resC = 8, resWaves = 8;
+    int exec = 0, tileC = 8, Kh = 16, tileW = 1, resC = 8, resWaves = 8;
 };
 
 // Tile tables for the temporally blocked executor: per grid, outputs of width
@@ -287,7 +291,8 @@ struct Plan {
 // Tiles of every grid, or of the grids skip[] does not mark.
 void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *skip = nullptr)
 {
-    const int L = p.tileC * 64;
+    const int wave_nodes = p.tileC * 64;
+    const int L = p.tileW * wave_nodes;
     const int W = L - 2 * p.Kh;
     std::vector<Tile> cls[3];
     int64_t o = 0;
@@ -300,8 +305,12 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
             t.out_hi = (int32_t)std::min<int64_t>(n, out + W);
             t.lo = (int32_t)std::max<int64_t>(0, out - p.Kh);
             t.hi = (int32_t)std::min<int64_t>(n, (int64_t)t.lo + L);
+            // node n-1 must not open a wave: its Mur update reads node n-2 by
+            // an in-wave move.  Start one node earlier (node -1 reads as zero
+            // and is never written); the tile still reaches n (see DESIGN).
+            if (t.hi == n && n - 1 > t.lo && (n - 1 - t.lo) % wave_nodes == 0) t.lo -= 1;
             int fl = 0;
-            if (t.lo == 0) fl |= TILE_LEFT_END;
+            if (t.lo <= 0) fl |= TILE_LEFT_END;
             if (t.hi == n) fl |= TILE_RIGHT_END;
             const int64_t s = d->src_cell[b];
             if (s >= t.lo && s < t.hi) fl |= TILE_SOURCE;
@@ -309,7 +318,7 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
                 const int64_t pc = d->probe_cells[b * d->n_probes + q];
                 if (pc >= t.out_lo && pc < t.out_hi) fl |= TILE_PROBE;
             }
-            for (int64_t k = t.lo; k < t.hi; ++k)
+            for (int64_t k = std::max<int64_t>(t.lo, 0); k < t.hi; ++k)
                 if (d->wp2[o + k] != 0.0) { fl |= TILE_PLASMA; break; }
             if (d->bc == FDTD_BC_CPML &&
                 (t.lo < d->cpml_cells + 1 || t.hi > n - 2 - d->cpml_cells))
@@ -402,6 +411,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
 
     // executor choice
     p.tileC = d->tile_cells ? d->tile_cells / 64 : (es == 8 ? 8 : 8);
+    p.tileW = d->tile_waves ? d->tile_waves : 1;
     p.Kh = d->steps_per_pass ? d->steps_per_pass : 16;
     p.resC = 8;
     p.resWaves = 8;   // 512-thread workgroups keep the FP64 coefficients in registers without spills
@@ -430,8 +440,8 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         if (p.nbins == 0) p.exec = FDTD_EXEC_TILED;      // nothing fits: plain tiles
     }
     if (p.exec == FDTD_EXEC_TILED || p.exec == FDTD_EXEC_MIXED) {
-        if (p.tileC * 64 <= 2 * p.Kh + 64)
-            return fail(FDTD_E_INVALID, "tile of %d nodes too small for halo %d", p.tileC * 64, p.Kh);
+        if (p.tileW * p.tileC * 64 <= 2 * p.Kh + 64)
+            return fail(FDTD_E_INVALID, "tile of %d nodes too small for halo %d", p.tileW * p.tileC * 64, p.Kh);
         // MIXED: tiles only for the grids the bins left out
         std::vector<char> binned(d->batch, 0);
         if (p.exec == FDTD_EXEC_MIXED)
@@ -574,14 +584,14 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                 (void)hipEventRecord(h->ev_fork, h->stream);
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
                 launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[2], h->ntiles[2], 2,
-                                h->tileC, (int)k, h->steps, slot, h->side);
+                                h->tileC, (int)k, h->steps, slot, h->side, h->tileW);
                 (void)hipEventRecord(h->ev_join, h->side);
             }
             for (int c = 0; c < 3; ++c)
                 if (h->ntiles[c] && !(fork && c == 2)) {
                     prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                     launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c,
-                                    h->tileC, (int)k, h->steps, slot, h->stream);
+                                    h->tileC, (int)k, h->steps, slot, h->stream, h->tileW);
                     prof_end(h);
                 }
             if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
@@ -610,7 +620,7 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                     if (h->ntiles[c]) {
                         prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                         launch_tiled<T>(g, s, cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC, kk,
-                                        h->steps + done, slot + (int)done, h->stream);
+                                        h->steps + done, slot + (int)done, h->stream, h->tileW);
                         prof_end(h);
                     }
                 cur ^= 1;
@@ -690,6 +700,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     h->psi_bytes = p.psi_bytes;
     h->exec = p.exec;
     h->tileC = p.tileC;
+    h->tileW = p.tileW;
     h->Kh = p.Kh;
     h->resC = p.resC;
     h->resWaves = p.resWaves;

@@ -179,7 +179,7 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
             ck.pE[i] = ck.pH[i] = (T)0;
             ck.bE[i] = ck.bH[i] = (T)1;
             ck.aE[i] = ck.aH[i] = (T)0;
-            if (k >= lim) continue;
+            if (k < 0 || k >= lim) continue;   // k = -1: a tile shifted off node 0
             int slot = -1, tab = 0;
             // E psi: nodes 1..P-1 and n-P..n-2 (depth d -> table d-1)
             if (k >= 1 && k < P) { tab = P - 1 - (int)k; slot = (int)k; }
@@ -421,6 +421,86 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
 
+// Workgroup tiles: one tile of WAVES * 64 * C nodes per workgroup, wave w
+// holding the w-th run of 64*C nodes.  Edge values cross waves through LDS
+// (two barriers per step, as in k_resident), so only the tile's two ends
+// carry a halo.  Every wave takes both exchanges once per step on either
+// path, so the barrier counts match.  The tile builder keeps node n-1 off
+// the first node of a wave (the Mur end reads its left neighbour with an
+// in-wave move).
+template <typename T, int C, int KLASS, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int cur, const Tile *tiles,
+                                                       int64_t ntiles, int nsteps, int64_t m0, int slot0)
+{
+    constexpr bool PLASMA = KLASS >= 1;
+    constexpr bool CPML = KLASS == 2;
+    __shared__ T ldsE[WAVES];
+    __shared__ T ldsH[WAVES];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;                  // whole workgroup: no barrier is left waiting
+    const Tile tl = tiles[t];
+    const int b = tl.grid;
+    const int64_t off = g.off[b], n = g.n[b];
+    const int64_t wave_lo = (int64_t)tl.lo + (int64_t)w * 64 * C;
+    const int64_t wave_hi = wave_lo + 64LL * C < tl.hi ? wave_lo + 64LL * C : tl.hi;
+    const int64_t k0 = wave_lo + (int64_t)lane * C;
+    Chunk<T, C, PLASMA, CPML> ck;
+    chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
+    ChunkRole role = chunk_role(g, b, n, k0, wave_lo, wave_hi > wave_lo ? wave_hi : wave_lo, C);
+    const bool probes = (tl.flags & TILE_PROBE) != 0;
+    auto er = [&](T e0) {
+        if (lane == 0) ldsE[w] = e0;
+        __syncthreads();
+        T v = shfl_down1(e0);
+        if (lane == 63) v = (w + 1 < WAVES) ? ldsE[w + 1] : (T)0;
+        return v;
+    };
+    auto hl = [&](T h) {
+        if (lane == 63) ldsH[w] = h;
+        __syncthreads();
+        T v = shfl_up1(h);
+        if (lane == 0) v = (w > 0) ? ldsH[w - 1] : (T)0;
+        return v;
+    };
+    if (!(role.left_any || role.right_any || role.src_any || probes)) {
+        for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
+    } else {
+        for (int st = 0; st < nsteps; ++st) {
+            chunk_step<T, C, PLASMA, CPML>(ck, g, role, m0 + st + 1, er, hl);
+            if (probes) chunk_probes<T, C>(g, b, k0, tl.out_lo, tl.out_hi, ck.E, slot0 + st);
+        }
+    }
+    chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
+}
+
+template <typename T, int C, int WAVES>
+void launch_tiledw_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
+                     int nsteps, int64_t m0, int slot0, hipStream_t st)
+{
+    const dim3 grid((unsigned)ntiles), blk(WAVES * 64);
+    if (klass == 0)
+        hipLaunchKernelGGL((k_tiledw<T, C, 0, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps, m0,
+                           slot0);
+    else if (klass == 1)
+        hipLaunchKernelGGL((k_tiledw<T, C, 1, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps, m0,
+                           slot0);
+    else
+        hipLaunchKernelGGL((k_tiledw<T, C, 2, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps, m0,
+                           slot0);
+}
+
+template <typename T, int WAVES>
+void launch_tiledw_w(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
+                     int C, int nsteps, int64_t m0, int slot0, hipStream_t st)
+{
+    switch (C) {
+    case 4: launch_tiledw_c<T, 4, WAVES>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
+    default: launch_tiledw_c<T, 8, WAVES>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
+    }
+}
+
 template <typename T, int C>
 void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
                     int klass, int nsteps, int64_t m0, int slot0, hipStream_t st)
@@ -439,8 +519,11 @@ void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int
 
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
-                  int C, int nsteps, int64_t m0, int slot0, hipStream_t st)
+                  int C, int nsteps, int64_t m0, int slot0, hipStream_t st, int waves)
 {
+    if (waves == 2) return launch_tiledw_w<T, 2>(g, s, cur, tiles, ntiles, klass, C, nsteps, m0, slot0, st);
+    if (waves == 4) return launch_tiledw_w<T, 4>(g, s, cur, tiles, ntiles, klass, C, nsteps, m0, slot0, st);
+    if (waves == 8) return launch_tiledw_w<T, 8>(g, s, cur, tiles, ntiles, klass, C, nsteps, m0, slot0, st);
     switch (C) {
     case 4: launch_tiled_c<T, 4>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
     case 8: launch_tiled_c<T, 8>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
@@ -450,9 +533,9 @@ void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64
 }
 
 template void launch_tiled<float>(const Grids &, State<float> &, int, const Tile *, int64_t, int, int,
-                                  int, int64_t, int, hipStream_t);
+                                  int, int64_t, int, hipStream_t, int);
 template void launch_tiled<double>(const Grids &, State<double> &, int, const Tile *, int64_t, int,
-                                   int, int, int64_t, int, hipStream_t);
+                                   int, int, int64_t, int, hipStream_t, int);
 
 // ------------------------------------------------------------- resident
 

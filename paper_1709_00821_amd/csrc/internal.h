@@ -82,9 +82,11 @@ template <typename T>
 void launch_step(const Grids &g, State<T> &s, int cur, int64_t total_nodes, int64_t m,
                  int slot, hipStream_t st);
 
+// Tiles of `waves` waves (1: one wave a tile, neighbours by DPP only; 2, 4,
+// 8: one workgroup a tile, neighbouring waves through LDS).
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
-                  int klass, int C, int nsteps, int64_t m0, int slot0, hipStream_t st);
+                  int klass, int C, int nsteps, int64_t m0, int slot0, hipStream_t st, int waves = 1);
 
 // Reads buffer cur, writes buffer out (cur itself for a whole-run resident
 // call, the other buffer when bins and tiles share a pass).

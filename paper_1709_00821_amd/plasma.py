@@ -21,7 +21,8 @@ def _as_list(problems) -> List[Problem1D]:
 
 
 def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: int = 0,
-              steps_per_pass: int = 0, checkpoint: int = 0, stream_handle: int = 0):
+              steps_per_pass: int = 0, checkpoint: int = 0, stream_handle: int = 0,
+              tile_waves: int = 0):
     """Build the C descriptor; returns (desc, arrays it points into)."""
     probs = _as_list(problems)
     p0 = probs[0]
@@ -59,6 +60,7 @@ def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: 
     d.probe_cells, d.freqs_hz = probes.ctypes.data, freqs.ctypes.data
     d.cpml_cells = p0.cpml_cells
     d.tile_cells = tile_cells
+    d.tile_waves = tile_waves
     d.cpml_m, d.cpml_sigma_max = p0.cpml_m, p0.cpml_sigma_max
     d.steps_per_pass = steps_per_pass
     d.stream = stream_handle or None
@@ -76,7 +78,7 @@ class FdtdPlasma:
     shape, probe count and DFT frequencies."""
 
     def __init__(self, problems: Union[Problem1D, Sequence[Problem1D]], precision: str = "f64",
-                 exec: str = "auto", tile_cells: int = 0, steps_per_pass: int = 0,
+                 exec: str = "auto", tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0,
                  checkpoint: int = 0, stream: Optional[torch.cuda.Stream] = None,
                  device: Union[int, str, torch.device] = "cuda"):
         probs = _as_list(problems)
@@ -86,7 +88,7 @@ class FdtdPlasma:
         self.cells = np.array([q.n for q in probs], np.int64)
         self.offsets = np.concatenate([[0], np.cumsum(self.cells)])
         d, self._keep = make_desc(probs, precision, exec, tile_cells, steps_per_pass, checkpoint,
-                                  self.stream.cuda_stream)
+                                  self.stream.cuda_stream, tile_waves)
         self.desc = d
         self.precision = precision
         self.workspace_bytes = workspace_bytes(d)

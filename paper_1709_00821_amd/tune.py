@@ -1,6 +1,6 @@
 """Launch-shape choice for the temporally blocked executor.
 
-pick() returns the (tile_cells, steps_per_pass) to use for a precision and
+pick() returns the (tile_cells, steps_per_pass, tile_waves) to use for a precision and
 grid size: an explicit override, else the best entry measured by
 `python -m paper_1709_00821_amd.tune` on this GPU (tuning.json next to this
 file), else a default.
@@ -12,59 +12,65 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_cells": 512, "steps_per_pass": 16}
+DEFAULT = {"tile_cells": 512, "steps_per_pass": 16, "tile_waves": 1}
 
 
 def _bucket(n: int) -> str:
     return "large" if n >= (1 << 20) else "small"
 
 
-def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0) -> dict:
+def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0) -> dict:
     out = dict(DEFAULT)
     if os.path.exists(CACHE):
         try:
             table = json.load(open(CACHE))
             ent = table.get("gfx950", {}).get(precision, {}).get(_bucket(n))
             if ent:
-                out.update({k: int(ent[k]) for k in ("tile_cells", "steps_per_pass")})
+                out.update({k: int(ent[k]) for k in ("tile_cells", "steps_per_pass", "tile_waves") if k in ent})
         except (OSError, ValueError, KeyError):
             pass
     if tile_cells:
         out["tile_cells"] = tile_cells
     if steps_per_pass:
         out["steps_per_pass"] = steps_per_pass
+    if tile_waves:
+        out["tile_waves"] = tile_waves
     return out
 
 
 def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
-          tiles=(256, 512, 768, 1024), depths=(8, 12, 16, 24, 32, 48, 64), log=print):
+          tiles=(256, 512, 768, 1024), depths=(8, 12, 16, 24, 32, 48, 64), waves=(1,), log=print):
     """Time run(steps) on a plasma/vacuum grid of n cells for every launch
-    shape; returns [(tile_cells, steps_per_pass, Mcell-updates/s)]."""
+    shape; returns [(tile_cells, steps_per_pass, tile_waves, Mcell-updates/s)]."""
     import torch
     from . import workloads as W
     from .plasma import FdtdPlasma
     p = W.large_c2(n=n, steps=steps)
     out = []
-    for tc in tiles:
-        for k in depths:
-            if tc <= 2 * k + 64:
+    for wv in waves:
+        for tc in tiles:
+            if wv > 1 and tc > 512:
                 continue
-            h = FdtdPlasma(p, precision=precision, exec="tiled", tile_cells=tc, steps_per_pass=k)
-            h.run(steps)
-            h.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(h.stream)
-            for _ in range(reps):
+            for k in depths:
+                if wv * tc <= 2 * k + 64:
+                    continue
+                h = FdtdPlasma(p, precision=precision, exec="tiled", tile_cells=tc, steps_per_pass=k,
+                               tile_waves=wv)
                 h.run(steps)
-            e1.record(h.stream)
-            e1.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            h.close()
-            rate = n * steps / (ms / 1e3) / 1e6
-            out.append((tc, k, rate))
-            log(f"tune {precision} tile_cells={tc:5d} steps_per_pass={k:3d}: {ms:8.3f} ms "
-                f"{rate:10.0f} Mcell/s")
+                h.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(h.stream)
+                for _ in range(reps):
+                    h.run(steps)
+                e1.record(h.stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                h.close()
+                rate = n * steps / (ms / 1e3) / 1e6
+                out.append((tc, k, wv, rate))
+                log(f"tune {precision} tile_cells={tc:5d} steps_per_pass={k:3d} tile_waves={wv}: "
+                    f"{ms:8.3f} ms {rate:10.0f} Mcell/s")
     return out
 
 
@@ -75,6 +81,9 @@ def main(argv=None):
     ap.add_argument("--cells", type=int, default=1 << 22)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--tiles", type=int, nargs="+", default=[256, 512, 768, 1024])
+    ap.add_argument("--depths", type=int, nargs="+", default=[8, 12, 16, 24, 32, 48, 64])
+    ap.add_argument("--waves", type=int, nargs="+", default=[1, 2, 4, 8])
     args = ap.parse_args(argv)
     table = {}
     if os.path.exists(args.out):
@@ -84,13 +93,14 @@ def main(argv=None):
             table = {}
     g = table.setdefault("gfx950", {})
     for prec in args.precision:
-        res = sweep(prec, n=args.cells, steps=args.steps, log=lambda m: print(m, flush=True))
-        tc, k, rate = max(res, key=lambda r: r[2])
-        g.setdefault(prec, {})["large"] = {"tile_cells": tc, "steps_per_pass": k,
+        res = sweep(prec, n=args.cells, steps=args.steps, tiles=tuple(args.tiles), depths=tuple(args.depths),
+                    waves=tuple(args.waves), log=lambda m: print(m, flush=True))
+        tc, k, wv, rate = max(res, key=lambda r: r[3])
+        g.setdefault(prec, {})["large"] = {"tile_cells": tc, "steps_per_pass": k, "tile_waves": wv,
                                           "mcells": round(rate, 1), "cells": args.cells,
                                           "steps": args.steps}
-        g[prec]["sweep"] = [[a, b, round(c, 1)] for a, b, c in res]
-        print(f"best {prec}: tile_cells={tc} steps_per_pass={k} {rate:.0f} Mcell/s", flush=True)
+        g[prec]["sweep"] = [[a, b, c, round(r, 1)] for a, b, c, r in res]
+        print(f"best {prec}: tile_cells={tc} steps_per_pass={k} tile_waves={wv} {rate:.0f} Mcell/s", flush=True)
     json.dump(table, open(args.out, "w"), indent=1)
 
 

@@ -224,16 +224,21 @@ def test_spectra_before_any_step_is_state_error(G):
         assert e.value.code == L.E_STATE
 
 
-@pytest.mark.parametrize("C,K", [(4, 4), (8, 16), (8, 32), (16, 8), (12, 20)])
-def test_tiled_geometries_bitwise(G, C, K):
-    """Every (tile width, halo depth) gives the bits of the per-step path."""
-    rng = np.random.default_rng(C * 100 + K)
-    probs = [W.random_slab(rng, n, n_freqs=4) for n in (64 * C - 1, 64 * C, 64 * C + 1, 5000)]
+@pytest.mark.parametrize("C,K,WV", [(4, 4, 1), (8, 16, 1), (8, 32, 1), (16, 8, 1), (12, 20, 1),
+                                    (4, 48, 4), (4, 32, 2), (8, 24, 4), (4, 12, 8)])
+def test_tiled_geometries_bitwise(G, C, K, WV):
+    """Every (tile width, halo depth, waves per tile) gives the bits of the
+    per-step path; grid lengths straddle the wave and tile boundaries, and
+    put node n-1 on the first node of a wave (the shifted tiles)."""
+    rng = np.random.default_rng(C * 100 + K + 7 * WV)
+    L = 64 * C
+    lens = sorted({L - 1, L, L + 1, 2 * L + 1, WV * L + 1, WV * L + L + 1, 5000})
+    probs = [W.random_slab(rng, n, n_freqs=4) for n in lens]
     probs = [q.copy(freqs=probs[0].freqs) for q in probs]
     T = 333
-    say(f"case tiled geometry C={C} K={K}")
+    say(f"case tiled geometry C={C} K={K} waves={WV} lens={lens}")
     Xs, Fs = gpu_run(G, probs, T, "f64", "step")
-    Xt, Ft = gpu_run(G, probs, T, "f64", "tiled", tile_cells=64 * C, steps_per_pass=K)
+    Xt, Ft = gpu_run(G, probs, T, "f64", "tiled", tile_cells=64 * C, steps_per_pass=K, tile_waves=WV)
     assert np.array_equal(Xs, Xt)
     for b in range(len(probs)):
         assert np.array_equal(Fs[b]["E"], Ft[b]["E"])
