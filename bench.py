@@ -33,10 +33,11 @@ def log(msg):
 
 
 def algorithmic_bytes_per_node(precision: str, plasma: bool) -> int:
-    """What one pass must move per node: read and write E, H (and J on plasma
-    nodes) once, plus the two FP64 material words (wp2, nu) on plasma nodes."""
+    """What one pass must move per node: read and write E, H once (and J, held
+    in FP64 at either precision, on plasma nodes), plus the two FP64 material
+    words (wp2, nu) on plasma nodes."""
     es = 8 if precision == "f64" else 4
-    return (2 * 3 * es + 16) if plasma else 2 * 2 * es
+    return (2 * 2 * es + 2 * 8 + 16) if plasma else 2 * 2 * es
 
 
 def run_precision(p, precision, T, K, W, tune):

@@ -75,7 +75,8 @@ enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RE
 
 typedef struct {
     uint32_t struct_size;        /* sizeof(fdtd_plasma_desc) */
-    int32_t precision;           /* FDTD_F64 | FDTD_F32 (E, H, J storage and curl arithmetic) */
+    int32_t precision;           /* FDTD_F64 | FDTD_F32: E, H storage and curl arithmetic (J and
+                                    its eq.(11) update are FP64 at either precision) */
     int32_t scheme;              /* FDTD_SCHEME_* */
     int32_t bc;                  /* FDTD_BC_* */
     int32_t exec;                /* FDTD_EXEC_* */

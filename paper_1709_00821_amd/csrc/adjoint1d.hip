@@ -83,8 +83,8 @@ __global__ void k_adj_source(const double *freqs, int F, double dt, const double
 // E^{n+1} of interior node k from the new H on both sides (k_step_e's
 // step_interior with the H values passed in); writes J^{n+1} if asked.
 template <typename T>
-__device__ __forceinline__ T e_from_h(const Grids &g, const T *E, const T *J, T hk, T hkm, int b, int64_t off,
-                                      int64_t k, int64_t m, T *Jn, bool write)
+__device__ __forceinline__ T e_from_h(const Grids &g, const T *E, const double *J, T hk, T hkm, int b,
+                                      int64_t off, int64_t k, int64_t m, double *Jn, bool write)
 {
     const T curl = hk - hkm;
     const T Eo = E[k];
@@ -99,7 +99,7 @@ __device__ __forceinline__ T e_from_h(const Grids &g, const T *E, const T *J, T 
     }
     if (k == g.src[b])
         En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
-    if (write) *Jn = (wp2 != 0.0) ? j_update<T>(J[k], Eo, En, c) : (T)0;
+    if (write) *Jn = (wp2 != 0.0) ? j_update<T>(J[k], (double)Eo, (double)En, c) : 0.0;
     return En;
 }
 
@@ -109,19 +109,21 @@ __device__ __forceinline__ T e_from_h(const Grids &g, const T *E, const T *J, T 
 // beside its neighbour) with the per-node functions and operation order of
 // k_step_h / k_step_e, so the recomputed states equal the forward run's bits.
 template <typename T>
-__global__ void k_recompute1d(Grids g, const T *E, const T *H, const T *J, T *En, T *Hn, T *Jn, int64_t total,
-                              int64_t m)
+__global__ void k_recompute1d(Grids g, const T *E, const T *H, const double *J, T *En, T *Hn, double *Jn,
+                              int64_t total, int64_t m)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const int b = grid_of_adj(g, i);
     const int64_t off = g.off[b], n = g.n[b], k = i - off;
     if (k >= n) return;
-    const T *Eg = E + off, *Hg = H + off, *Jg = J + off;
+    const T *Eg = E + off, *Hg = H + off;
+    const double *Jg = J + off;
     const T ch = (T)g.ch;
     auto hnew = [&](int64_t j) { return h_update<T>(Hg[j], Eg[j], Eg[j + 1], ch); };
     if (k <= n - 2) Hn[off + k] = hnew(k);
-    T e, jn = (T)0;
+    T e;
+    double jn = 0.0;
     if (k == 0 || k == n - 1) {
         if (g.bc == 0) {  // first-order Mur: E0' = E1 + cm (E1' - E0)
             const int64_t kn = (k == 0) ? 1 : n - 2;
@@ -138,23 +140,24 @@ __global__ void k_recompute1d(Grids g, const T *E, const T *H, const T *J, T *En
 }
 
 template <typename T>
-void launch_recompute1d(const Grids &g, const T *E, const T *H, const T *J, T *En, T *Hn, T *Jn, int64_t total,
-                        int64_t m, hipStream_t st)
+void launch_recompute1d(const Grids &g, const T *E, const T *H, const double *J, T *En, T *Hn, double *Jn,
+                        int64_t total, int64_t m, hipStream_t st)
 {
     hipLaunchKernelGGL(k_recompute1d<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g, E, H, J, En,
                        Hn, Jn, total, m);
 }
 
-template void launch_recompute1d<float>(const Grids &, const float *, const float *, const float *, float *,
-                                        float *, float *, int64_t, int64_t, hipStream_t);
-template void launch_recompute1d<double>(const Grids &, const double *, const double *, const double *, double *,
-                                         double *, double *, int64_t, int64_t, hipStream_t);
+template void launch_recompute1d<float>(const Grids &, const float *, const float *, const double *, float *,
+                                        float *, double *, int64_t, int64_t, hipStream_t);
+template void launch_recompute1d<double>(const Grids &, const double *, const double *, const double *,
+                                         double *, double *, double *, int64_t, int64_t, hipStream_t);
 
 template <typename T>
 struct AdjView {
     const T *lE, *lH, *lJ;      // lambda^{m+1}
     T *nE, *nH, *nJ;            // lambda^m
-    const T *En, *Jn;           // forward E^m, J^m
+    const T *En;                // forward E^m
+    const double *Jn;           // forward J^m (FP64)
     const T *Hh, *En1;          // forward H^{m+1/2}, E^{m+1}
 };
 
@@ -243,7 +246,7 @@ void launch_adj_source(const double *freqs, int F, double dt, const double2 *G, 
 
 template <typename T>
 void launch_adj_step(const Grids &g, const T *const lam[3], T *const out[3], const T *En,
-                     const T *Jn, const T *Hh, const T *En1, const double *tab, int64_t total,
+                     const double *Jn, const T *Hh, const T *En1, const double *tab, int64_t total,
                      const double *gsrc, int64_t T_, int64_t m, int probe, double *grad,
                      hipStream_t st)
 {
@@ -253,7 +256,7 @@ void launch_adj_step(const Grids &g, const T *const lam[3], T *const out[3], con
 }
 
 template void launch_adj_step<float>(const Grids &, const float *const[3], float *const[3],
-                                     const float *, const float *, const float *, const float *,
+                                     const float *, const double *, const float *, const float *,
                                      const double *, int64_t, const double *, int64_t, int64_t, int,
                                      double *, hipStream_t);
 template void launch_adj_step<double>(const Grids &, const double *const[3], double *const[3],

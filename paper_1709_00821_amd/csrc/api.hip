@@ -127,8 +127,8 @@ struct fdtd_plasma {
     bool ck_on = false;        // the advance in progress stores checkpoints
     bool ck_valid = false;     // the state is a checkpointed run() of ck_run steps
     int64_t ck_run = 0;
-    char *d_ck = nullptr;      // [ck_n][3][state_bytes]
-    char *d_seg = nullptr;     // [ck_s + 1][3][state_bytes]
+    char *d_ck = nullptr;      // [ck_n][3][slot_bytes]: E, H, J
+    char *d_seg = nullptr;     // [ck_s + 1][3][slot_bytes]
     void *d_lam[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     double *d_grad = nullptr, *d_tab = nullptr, *d_gsrc = nullptr, *d_loss = nullptr;
     double2 *d_xref = nullptr, *d_G = nullptr;
@@ -180,7 +180,7 @@ struct fdtd_plasma {
         for (int i = 0; i < 2; ++i) {
             s.E[i] = (T *)d_E[i];
             s.H[i] = (T *)d_H[i];
-            s.J[i] = (T *)d_J[i];
+            s.J[i] = (double *)d_J[i];
             s.psiE[i] = (T *)d_psiE[i];
             s.psiH[i] = (T *)d_psiH[i];
         }
@@ -475,7 +475,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     for (int i = 0; i < 2; ++i) {
         p.o_E[i] = L.take(p.state_bytes);
         p.o_H[i] = L.take(p.state_bytes);
-        p.o_J[i] = L.take(p.state_bytes);
+        p.o_J[i] = L.take(8 * p.nodes);            // J in FP64 at either precision
         p.o_psiE[i] = L.take(p.psi_bytes);
         p.o_psiH[i] = L.take(p.psi_bytes);
     }
@@ -486,7 +486,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         p.ck_T = d->checkpoint_steps;
         p.ck_s = (int64_t)std::ceil(std::sqrt((double)p.ck_T));
         p.ck_n = p.ck_T / p.ck_s + 1;
-        const int64_t st3 = 3 * round_up(p.state_bytes, kAlign);
+        const int64_t st3 = 3 * round_up(8 * p.nodes, kAlign);    // E, H, J slots sized for J
         p.o_ck = L.take(p.ck_n * st3);
         p.o_seg = L.take((p.ck_s + 1) * st3);
         for (int i = 0; i < 2; ++i)
@@ -506,7 +506,7 @@ void zero_state(fdtd_plasma *h)
     for (int i = 0; i < 2; ++i) {
         launch_fill(h->d_E[i], round_up(h->state_bytes, 16), h->stream);
         launch_fill(h->d_H[i], round_up(h->state_bytes, 16), h->stream);
-        launch_fill(h->d_J[i], round_up(h->state_bytes, 16), h->stream);
+        launch_fill(h->d_J[i], round_up(8 * h->nodes, 16), h->stream);
         launch_fill(h->d_psiE[i], round_up(h->psi_bytes, 16), h->stream);
         launch_fill(h->d_psiH[i], round_up(h->psi_bytes, 16), h->stream);
     }
@@ -554,17 +554,17 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
     const Grids g = h->grids();
     State<T> s = h->state<T>();
     int64_t left = nsteps;
-    const int64_t ck3 = 3 * round_up(h->state_bytes, kAlign);
+    const int64_t ck3 = 3 * round_up(8 * h->nodes, kAlign);
     while (left > 0) {
         const int slot = (int)(h->steps - h->win_base);
         int64_t room = h->SB - slot;
         if (h->ck_on) {
             if (h->steps % h->ck_s == 0 && h->steps / h->ck_s < h->ck_n) {
                 char *dst = h->d_ck + (h->steps / h->ck_s) * ck3;
-                const int64_t sb = round_up(h->state_bytes, kAlign);
+                const int64_t sb = round_up(8 * h->nodes, kAlign);
                 launch_copy(dst, h->d_E[h->cur], round_up(h->state_bytes, 16), h->stream);
                 launch_copy(dst + sb, h->d_H[h->cur], round_up(h->state_bytes, 16), h->stream);
-                launch_copy(dst + 2 * sb, h->d_J[h->cur], round_up(h->state_bytes, 16), h->stream);
+                launch_copy(dst + 2 * sb, h->d_J[h->cur], round_up(8 * h->nodes, 16), h->stream);
             }
             room = std::min<int64_t>(room, h->ck_s - h->steps % h->ck_s);
         }
@@ -948,9 +948,8 @@ int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, d
     if (rc) return rc;
     if (grid < 0 || grid >= h->batch) return fail(FDTD_E_INVALID, "grid %lld out of range", (long long)grid);
     const int64_t n = h->cells[grid], o = h->off[grid];
-    const int es = h->esize;
-    std::vector<char> buf(n * es);
-    auto fetch = [&](void *base, double *dst, int64_t cnt) -> int {
+    std::vector<char> buf(n * 8);
+    auto fetch = [&](void *base, double *dst, int64_t cnt, int es) -> int {
         if (!dst) return FDTD_OK;
         HIP_TRY(hipMemcpyAsync(buf.data(), (char *)base + o * es, cnt * es, hipMemcpyDeviceToHost,
                                h->stream));
@@ -959,9 +958,9 @@ int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, d
             dst[k] = es == 8 ? ((double *)buf.data())[k] : (double)((float *)buf.data())[k];
         return FDTD_OK;
     };
-    if ((rc = fetch(h->d_E[h->cur], E, n))) return rc;
-    if ((rc = fetch(h->d_H[h->cur], H, n - 1))) return rc;
-    if ((rc = fetch(h->d_J[h->cur], J, n))) return rc;
+    if ((rc = fetch(h->d_E[h->cur], E, n, h->esize))) return rc;
+    if ((rc = fetch(h->d_H[h->cur], H, n - 1, h->esize))) return rc;
+    if ((rc = fetch(h->d_J[h->cur], J, n, 8))) return rc;
     return FDTD_OK;
 }
 
@@ -1001,10 +1000,10 @@ int reverse_sweep(fdtd_plasma *h, int64_t Tn, int probe)
     Grids g = h->grids();
     Grids gq = g;
     gq.P = 0;                          // recompute: no probe samples
-    const int64_t sb = round_up(h->state_bytes, kAlign), ck3 = 3 * sb;
+    const int64_t sb = round_up(8 * h->nodes, kAlign), ck3 = 3 * sb;
     auto segE = [&](int64_t i) { return (T *)(h->d_seg + i * ck3); };
     auto segH = [&](int64_t i) { return (T *)(h->d_seg + i * ck3 + sb); };
-    auto segJ = [&](int64_t i) { return (T *)(h->d_seg + i * ck3 + 2 * sb); };
+    auto segJ = [&](int64_t i) { return (double *)(h->d_seg + i * ck3 + 2 * sb); };
     for (int i = 0; i < 2; ++i)
         for (int q = 0; q < 3; ++q) launch_fill(h->d_lam[i][q], round_up(h->state_bytes, 16), h->stream);
     launch_fill(h->d_grad, round_up(8 * h->nodes, 16), h->stream);

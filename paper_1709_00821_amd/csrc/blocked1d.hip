@@ -25,7 +25,8 @@ namespace fdtdp {
 template <typename T, int C, bool PLASMA, bool CPML>
 struct Chunk {
     T E[C], H[C];
-    T J[PLASMA ? C : 1];
+    double J[PLASMA ? C : 1];      // the current, held in FP64
+    double Ed[PLASMA ? C : 1];     // E^n widened to FP64 (the J update's E_old), kept across steps
     NodeCoef<T> cf[PLASMA ? C : 1];
     uint32_t pmask;                // bit i: node i is plasma
     T pE[CPML ? C : 1], pH[CPML ? C : 1];
@@ -160,7 +161,9 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
     load_chunk<T, C>(s.H[buf] + off, k0, lim, ck.H);
     ck.pmask = 0;
     if constexpr (PLASMA) {
-        load_chunk<T, C>(s.J[buf] + off, k0, lim, ck.J);
+        load_chunk<double, C>(s.J[buf] + off, k0, lim, ck.J);
+#pragma unroll
+        for (int i = 0; i < C; ++i) ck.Ed[i] = (double)ck.E[i];
         double w[C], v[C];
         load_chunk<double, C>(g.wp2 + off, k0, lim, w);
         load_chunk<double, C>(g.nu + off, k0, lim, v);
@@ -211,7 +214,7 @@ __device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML> &ck,
 {
     store_chunk<T, C>(s.E[buf] + off, k0, lo, hi, ck.E);
     store_chunk<T, C>(s.H[buf] + off, k0, lo, hi < n ? hi : n - 1, ck.H);   // H has n-1 nodes
-    if constexpr (PLASMA) store_chunk<T, C>(s.J[buf] + off, k0, lo, hi, ck.J);
+    if constexpr (PLASMA) store_chunk<double, C>(s.J[buf] + off, k0, lo, hi, ck.J);
     if constexpr (CPML) {
         const int P = g.cpmlP;
 #pragma unroll
@@ -250,10 +253,9 @@ __device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er, T c
 }
 
 // E^{n+1} (before the source) of the chunk; Hl = H of the node before the
-// chunk.  Eo receives E^n when PLASMA.
+// chunk.
 template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T ce,
-                                        T (&Eo)[PLASMA ? C : 1])
+__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T ce)
 {
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -266,7 +268,6 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T c
         }
         if constexpr (PLASMA) {
             // the plasma formula reproduces the vacuum update at vacuum nodes
-            Eo[i] = ck.E[i];
             ck.E[i] = e_update_plasma(ck.E[i], ck.J[i], curl, ck.cf[i]);
         } else {
             ck.E[i] = e_update_vac<T>(ck.E[i], curl, ce);
@@ -274,13 +275,20 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T c
     }
 }
 
-// J update of the chunk; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.
+// J update of the chunk (after the source), with E_old the FP64 copy of E^n
+// kept from the previous step; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.
+// The Mur ends rewrite E after this and leave their copy stale, which is
+// harmless: end nodes carry no plasma (b1 = 0).
 template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML> &ck, const T (&Eo)[PLASMA ? C : 1])
+__device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML> &ck)
 {
     if constexpr (PLASMA) {
 #pragma unroll
-        for (int i = 0; i < C; ++i) ck.J[i] = j_update<T>(ck.J[i], Eo[i], ck.E[i], ck.cf[i]);
+        for (int i = 0; i < C; ++i) {
+            const double en = (double)ck.E[i];
+            ck.J[i] = j_update<T>(ck.J[i], ck.Ed[i], en, ck.cf[i]);
+            ck.Ed[i] = en;
+        }
     }
 }
 
@@ -290,9 +298,8 @@ __device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, 
                                                  GetEr get_er, GetHl get_hl)
 {
     chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
-    T Eo[PLASMA ? C : 1];
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce, Eo);
-    chunk_j<T, C, PLASMA, CPML>(ck, Eo);
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
+    chunk_j<T, C, PLASMA, CPML>(ck);
 }
 
 // Everything a lane needs to know about the grid ends, source and probes in
@@ -325,13 +332,12 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const 
         eoR1 = choose<T>(role.iright >= 1, pick<T, C>(ck.E, role.iright - 1), prevLast);
     }
     chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), ch);
-    T Eo[PLASMA ? C : 1];
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), ce, Eo);
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), ce);
     if (role.src_any) {
         const double sv = source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp);
         if (role.isrc >= 0) put<T, C>(ck.E, role.isrc, add_source<T>(pick<T, C>(ck.E, role.isrc), sv));
     }
-    chunk_j<T, C, PLASMA, CPML>(ck, Eo);
+    chunk_j<T, C, PLASMA, CPML>(ck);
     if (role.left_any && role.ileft >= 0) {
         const T en1 = choose<T>(il, ck.E[2], ck.E[1]);
         const T v = (g.bc == 0) ? (T)(eo1 + (T)g.cm * (en1 - eo0)) : (T)0;
@@ -410,7 +416,14 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     auto er = [](T e0) { return shfl_down1(e0); };
     auto hl = [](T h) { return shfl_up1(h); };
     if (!(role.left_any || role.right_any || role.src_any || probes)) {
-        for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
+        // two steps per trip: the loop-carried E copies then alternate
+        // registers instead of being moved back every step
+        int st = 0;
+        for (; st + 2 <= nsteps; st += 2) {
+            chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
+            chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
+        }
+        if (st < nsteps) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
     } else {
         for (int st = 0; st < nsteps; ++st) {
             chunk_step<T, C, PLASMA, CPML>(ck, g, role, m0 + st + 1, er, hl);
@@ -567,7 +580,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
     if (active) chunk_load<T, C, true, false>(ck, g, s, cur, b, off, n, k0, n);
     else {
 #pragma unroll
-        for (int i = 0; i < C; ++i) { ck.E[i] = ck.H[i] = ck.J[i] = (T)0; }
+        for (int i = 0; i < C; ++i) {
+            ck.E[i] = ck.H[i] = (T)0;
+            ck.J[i] = ck.Ed[i] = 0.0;
+        }
         ck.pmask = 0;
     }
     ChunkRole role = active ? chunk_role(g, b, n, k0, wave_lo < 0 ? 0 : wave_lo, wave_hi, C)

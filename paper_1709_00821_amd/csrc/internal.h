@@ -36,7 +36,7 @@ template <typename T>
 struct State {
     T *E[2];
     T *H[2];
-    T *J[2];
+    double *J[2];           // the plasma current is held in FP64 at either field precision
     T *psiE[2];             // [batch][2][P]: left zone then right zone
     T *psiH[2];
 };
@@ -112,14 +112,14 @@ void launch_adj_source(const double *freqs, int F, double dt, const double2 *G, 
                        int64_t T, double *gsrc, hipStream_t st);
 template <typename T>
 void launch_adj_step(const Grids &g, const T *const lam[3], T *const out[3], const T *En,
-                     const T *Jn, const T *Hh, const T *En1, const double *tab, int64_t total,
+                     const double *Jn, const T *Hh, const T *En1, const double *tab, int64_t total,
                      const double *gsrc, int64_t T_, int64_t m, int probe, double *grad,
                      hipStream_t st);
 void launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
 // One forward step (Mur/PEC ends, no probes) as a single launch, for the
 // reverse sweep's recompute; same bits as launch_step.
 template <typename T>
-void launch_recompute1d(const Grids &g, const T *E, const T *H, const T *J, T *En, T *Hn, T *Jn, int64_t total,
-                        int64_t m, hipStream_t st);
+void launch_recompute1d(const Grids &g, const T *E, const T *H, const double *J, T *En, T *Hn, double *Jn,
+                        int64_t total, int64_t m, hipStream_t st);
 
 }  // namespace fdtdp

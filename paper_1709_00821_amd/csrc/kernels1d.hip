@@ -112,7 +112,7 @@ __device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, in
     if (k == g.src[b])
         En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
     if (write) {
-        s.J[nxt][off + k] = (wp2 != 0.0) ? j_update<T>(s.J[cur][off + k], Eo, En, c) : (T)0;
+        s.J[nxt][off + k] = (wp2 != 0.0) ? j_update<T>(s.J[cur][off + k], (double)Eo, (double)En, c) : 0.0;
     }
     return En;
 }
@@ -137,7 +137,7 @@ __global__ void k_step_e(Grids g, State<T> s, int cur, int64_t total, int64_t m,
         } else {
             En = (T)0;
         }
-        s.J[nxt][off + k] = (T)0;
+        s.J[nxt][off + k] = 0.0;
     } else {
         En = step_interior<T>(g, s, cur, b, off, n, k, m, true);
     }

@@ -274,9 +274,9 @@ __device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, cons
     if (!g.py && j == 0) { e0 = zero; e2 = zero; }
     if (k == 0) { e0 = zero; e1 = zero; }
     if (plasma) {
-        pl.J[0][cq] = j_update<T>(pl.J[0][cq], eo0, e0, c0);
-        pl.J[1][cq] = j_update<T>(pl.J[1][cq], eo1, e1, c1);
-        pl.J[2][cq] = j_update<T>(pl.J[2][cq], eo2, e2, c2);
+        pl.J[0][cq] = (T)j_update<T>((double)pl.J[0][cq], (double)eo0, (double)e0, c0);
+        pl.J[1][cq] = (T)j_update<T>((double)pl.J[1][cq], (double)eo1, (double)e1, c1);
+        pl.J[2][cq] = (T)j_update<T>((double)pl.J[2][cq], (double)eo2, (double)e2, c2);
     }
 }
 

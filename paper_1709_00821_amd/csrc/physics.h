@@ -224,18 +224,19 @@ __device__ __forceinline__ double e_update_plasma(double E, double J, double cur
 {
     return fmat(-c.eH, curl, fmat(-c.eJ, J, c.eA * E));
 }
-__device__ __forceinline__ float e_update_plasma(float E, float J, float curl,
+__device__ __forceinline__ float e_update_plasma(float E, double J, float curl,
                                                  const NodeCoef<float> &c)
 {
-    return fmat(-c.eH, curl, fmat(-c.eJ, J, fmat(c.eA, E, E)));
+    return fmat(-c.eH, curl, fmat(-c.eJ, (float)J, fmat(c.eA, E, E)));
 }
 
-// J_new = a J + b1 E_old + b2 E_new, in FP64 for both storage precisions
-// (eq.(11): the exp(-nu dt) fractions keep their FP64 accuracy).
+// J_new = a J + b1 E_old + b2 E_new in FP64 for both field precisions: J is
+// held in FP64 (eq.(11): the exp(-nu dt) fractions and the current they
+// accumulate keep their FP64 accuracy); the E values enter already widened.
 template <typename T>
-__device__ __forceinline__ T j_update(T J, T Eold, T Enew, const NodeCoef<T> &c)
+__device__ __forceinline__ double j_update(double J, double Eold, double Enew, const NodeCoef<T> &c)
 {
-    return (T)__builtin_fma(c.b2, (double)Enew, __builtin_fma(c.b1, (double)Eold, c.a * (double)J));
+    return __builtin_fma(c.b2, Enew, __builtin_fma(c.b1, Eold, c.a * J));
 }
 
 }  // namespace fdtdp
