@@ -83,7 +83,7 @@ struct fdtd_plasma {
     // device pointers into the workspace
     int64_t *d_off = nullptr, *d_n = nullptr, *d_src = nullptr, *d_probe = nullptr;
     double *d_wp2 = nullptr, *d_nu = nullptr, *d_freqs = nullptr, *d_samp = nullptr,
-           *d_cpml = nullptr;
+           *d_cpml = nullptr, *d_srcv = nullptr;
     double2 *d_X = nullptr, *d_Xtmp = nullptr, *d_tw = nullptr;
     void *d_E[2] = {nullptr, nullptr}, *d_H[2] = {nullptr, nullptr}, *d_J[2] = {nullptr, nullptr};
     void *d_psiE[2] = {nullptr, nullptr}, *d_psiH[2] = {nullptr, nullptr};
@@ -170,6 +170,7 @@ struct fdtd_plasma {
         g.src_t0 = d.src_t0;
         g.src_amp = d.src_amp;
         g.cpml = d_cpml;
+        g.srcv = d_srcv;
         return g;
     }
 
@@ -269,7 +270,7 @@ int validate(const fdtd_plasma_desc *d)
 
 struct Plan {
     Layout L;
-    int64_t o_off = 0, o_n = 0, o_src = 0, o_probe = 0, o_wp2 = 0, o_nu = 0, o_freqs = 0, o_samp = 0,
+    int64_t o_off = 0, o_n = 0, o_src = 0, o_probe = 0, o_wp2 = 0, o_nu = 0, o_freqs = 0, o_samp = 0, o_srcv = 0,
             o_X = 0, o_Xtmp = 0, o_tw = 0, o_cpml = 0;
     int64_t o_E[2] = {0, 0}, o_H[2] = {0, 0}, o_J[2] = {0, 0}, o_psiE[2] = {0, 0}, o_psiH[2] = {0, 0};
     int64_t o_tiles = 0, o_slots = 0;
@@ -468,6 +469,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     p.o_wp2 = L.take(8 * p.nodes);
     p.o_nu = L.take(8 * p.nodes);
     p.o_samp = L.take(8 * d->batch * P * (int64_t)p.SB);
+    p.o_srcv = L.take(8 * (int64_t)p.SB);
     p.o_X = L.take(16 * d->batch * P * (int64_t)F);
     p.o_Xtmp = L.take(16 * d->batch * P * (int64_t)F);
     p.o_tw = L.take(16 * (int64_t)std::min(p.SB, kTwiddleChunk) * F);
@@ -558,6 +560,13 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
     while (left > 0) {
         const int slot = (int)(h->steps - h->win_base);
         int64_t room = h->SB - slot;
+        // a new sample window: source values of all its steps, read by the
+        // register-tile kernels
+        if (slot == 0) {
+            prof_begin(h, "source_table", 0);
+            launch_src_table(g, h->steps + 1, h->SB, h->d_srcv, h->stream);
+            prof_end(h);
+        }
         if (h->ck_on) {
             if (h->steps % h->ck_s == 0 && h->steps / h->ck_s < h->ck_n) {
                 char *dst = h->d_ck + (h->steps / h->ck_s) * ck3;
@@ -584,14 +593,14 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                 (void)hipEventRecord(h->ev_fork, h->stream);
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
                 launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[2], h->ntiles[2], 2,
-                                h->tileC, (int)k, h->steps, slot, h->side, h->tileW);
+                                h->tileC, (int)k, slot, h->side, h->tileW);
                 (void)hipEventRecord(h->ev_join, h->side);
             }
             for (int c = 0; c < 3; ++c)
                 if (h->ntiles[c] && !(fork && c == 2)) {
                     prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                     launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c,
-                                    h->tileC, (int)k, h->steps, slot, h->stream, h->tileW);
+                                    h->tileC, (int)k, slot, h->stream, h->tileW);
                     prof_end(h);
                 }
             if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
@@ -609,8 +618,8 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
             }
             prof_begin(h, "resident", h->class_nodes[3]);
-            launch_resident<T>(g, s, h->cur, out, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k,
-                               h->steps, slot, rs);
+            launch_resident<T>(g, s, h->cur, out, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k, slot,
+                               rs);
             prof_end(h);
             if (fork) (void)hipEventRecord(h->ev_join, h->side);
             int cur = h->cur;
@@ -620,7 +629,7 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                     if (h->ntiles[c]) {
                         prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                         launch_tiled<T>(g, s, cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC, kk,
-                                        h->steps + done, slot + (int)done, h->stream, h->tileW);
+                                        slot + (int)done, h->stream, h->tileW);
                         prof_end(h);
                     }
                 cur ^= 1;
@@ -630,8 +639,8 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
         } else {
             k = std::min<int64_t>(left, room);
             prof_begin(h, "resident", h->real_nodes);
-            launch_resident<T>(g, s, h->cur, h->cur, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k,
-                               h->steps, slot, h->stream);
+            launch_resident<T>(g, s, h->cur, h->cur, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k, slot,
+                               h->stream);
             prof_end(h);
         }
         if (h->exec != FDTD_EXEC_RESIDENT) h->cur ^= 1;
@@ -760,6 +769,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     h->d_wp2 = (double *)(w + p.o_wp2);
     h->d_nu = (double *)(w + p.o_nu);
     h->d_samp = (double *)(w + p.o_samp);
+    h->d_srcv = (double *)(w + p.o_srcv);
     h->d_X = (double2 *)(w + p.o_X);
     h->d_Xtmp = (double2 *)(w + p.o_Xtmp);
     h->d_tw = (double2 *)(w + p.o_tw);

@@ -302,52 +302,116 @@ __device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, 
     chunk_j<T, C, PLASMA, CPML>(ck);
 }
 
-// Everything a lane needs to know about the grid ends, source and probes in
-// its chunk (computed once per launch).
-struct ChunkRole {
-    int isrc;        // index of the source node in the chunk, or -1
-    int ileft;       // index of node 0 in the chunk (0 or 1; node 1 follows it), or -1
-    int iright;      // index of node n-1 in the chunk, or -1
-    bool right_any;  // some lane of the wave holds node n-1
-    bool left_any;
-    bool src_any;
+// Where a grid's special nodes sit in one wave's span of 64*C nodes, as
+// positions counted from the wave's first node (lane pos / C, register
+// pos % C); -1 when the wave does not hold the node.  The values are the same
+// in every lane (read through readfirstlane), so the register selects below
+// run on scalar conditions and the branches on them are scalar.
+struct WaveRole {
+    int left;    // node 0: 0 or 1 (a wave never starts left of node -1)
+    int right;   // node n-1: never register 0 of lane 0 (see the tile builder)
+    int src;     // the source node
 };
 
-// One full time step of a lane's chunk.  Er / Hl come from the neighbours;
-// the caller supplies them through get_er() / get_hl() so both kernels share
-// this body.
+__device__ __forceinline__ int uniform(int64_t v) { return __builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ __forceinline__ WaveRole wave_role(const Grids &g, int b, int64_t n, int64_t wave_lo,
+                                              int64_t wave_hi)
+{
+    WaveRole r;
+    r.left = uniform((wave_lo <= 0 && 0 < wave_hi) ? -wave_lo : -1);
+    r.right = uniform((n - 1 >= wave_lo && n - 1 < wave_hi) ? n - 1 - wave_lo : -1);
+    const int64_t s = g.src[b];
+    r.src = uniform((s >= 0 && s >= wave_lo && s < wave_hi) ? s - wave_lo : -1);
+    return r;
+}
+
+__device__ __forceinline__ bool has_role(const WaveRole &r) { return r.left >= 0 || r.right >= 0 || r.src >= 0; }
+
+// v[i] for a wave-uniform i in [0, C).  The registers are gathered into one
+// vector value and indexed there, which gfx950 code generation turns into
+// C - 1 selects on scalar conditions.  (Selecting between the array elements
+// directly would be folded into one load through a selected address and force
+// the array into scratch memory.)
+template <typename T, int C>
+__device__ __forceinline__ T upick(const T (&v)[C], int i)
+{
+    typedef T vec __attribute__((ext_vector_type(C)));
+    vec x;
+#pragma unroll
+    for (int j = 0; j < C; ++j) x[j] = v[j];
+    return x[i];
+}
+
+// v[i] = x in the lanes where `here` holds (i wave-uniform).
+template <typename T, int C>
+__device__ __forceinline__ void uput(T (&v)[C], int i, bool here, T x)
+{
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = (here && i == j) ? x : v[j];
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(v.x, l),
+                                                __builtin_amdgcn_readlane(v.y, l)));
+}
+
+// The end values the Mur updates read, E^n at nodes 0, 1 and n-1, n-2, held
+// from one step to the next: each equals what the previous step wrote (the
+// end node) or read (its neighbour, which later sub-steps of that step leave
+// alone).  Meaningful only in the lane holding the end.
+template <typename T>
+struct EndCarry {
+    T e0, e1, eR, eR1;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, EndCarry<T> &c)
+{
+    c.e0 = c.e1 = c.eR = c.eR1 = (T)0;
+    if (r.left >= 0) {
+        c.e0 = r.left ? E[1] : E[0];
+        c.e1 = r.left ? E[2] : E[1];
+    }
+    if (r.right >= 0) {
+        const int ir = r.right % C;
+        c.eR = upick<T, C>(E, ir);
+        c.eR1 = ir ? upick<T, C>(E, ir - 1) : shfl_up1(E[C - 1]);
+    }
+}
+
+// One full time step of a wave holding a grid end or the source: H, E, the
+// source (added to E^{n+1}, eq.(15), before the J update), J, then the ends
+// (first-order Mur, or PEC E = 0).  sv: the source value of this step.
 template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
 __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
-                                           const ChunkRole &role, int64_t m, GetEr get_er,
-                                           GetHl get_hl)
+                                           const WaveRole &r, int lane, EndCarry<T> &c, double sv,
+                                           GetEr get_er, GetHl get_hl)
 {
-    const T ch = (T)g.ch, ce = (T)g.ce;
-    // E^n values the Mur ends need
-    const int il = role.ileft > 0 ? 1 : 0;
-    T eo0 = choose<T>(il, ck.E[1], ck.E[0]), eo1 = choose<T>(il, ck.E[2], ck.E[1]);
-    T eoR = (T)0, eoR1 = (T)0;
-    if (role.right_any) {
-        const T prevLast = shfl_up1(ck.E[C - 1]);
-        eoR = pick<T, C>(ck.E, role.iright < 0 ? 0 : role.iright);
-        eoR1 = choose<T>(role.iright >= 1, pick<T, C>(ck.E, role.iright - 1), prevLast);
-    }
-    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), ch);
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), ce);
-    if (role.src_any) {
-        const double sv = source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp);
-        if (role.isrc >= 0) put<T, C>(ck.E, role.isrc, add_source<T>(pick<T, C>(ck.E, role.isrc), sv));
+    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
+    if (r.src >= 0) {
+        const int is = r.src % C;
+        uput<T, C>(ck.E, is, lane == r.src / C, add_source<T>(upick<T, C>(ck.E, is), sv));
     }
     chunk_j<T, C, PLASMA, CPML>(ck);
-    if (role.left_any && role.ileft >= 0) {
-        const T en1 = choose<T>(il, ck.E[2], ck.E[1]);
-        const T v = (g.bc == 0) ? (T)(eo1 + (T)g.cm * (en1 - eo0)) : (T)0;
-        if (il) ck.E[1] = v; else ck.E[0] = v;
+    if (r.left >= 0) {
+        const T en1 = r.left ? ck.E[2] : ck.E[1];
+        const T v = (g.bc == 0) ? (T)(c.e1 + (T)g.cm * (en1 - c.e0)) : (T)0;
+        if (r.left) ck.E[1] = (lane == 0) ? v : ck.E[1];
+        else ck.E[0] = (lane == 0) ? v : ck.E[0];
+        c.e0 = v;
+        c.e1 = en1;
     }
-    if (role.right_any) {
-        const T prevLast = shfl_up1(ck.E[C - 1]);
-        const T enR1 = choose<T>(role.iright >= 1, pick<T, C>(ck.E, role.iright - 1), prevLast);
-        if (role.iright >= 0)
-            put<T, C>(ck.E, role.iright, (g.bc == 0) ? (T)(eoR1 + (T)g.cm * (enR1 - eoR)) : (T)0);
+    if (r.right >= 0) {
+        const int ir = r.right % C;
+        const T en1 = ir ? upick<T, C>(ck.E, ir - 1) : shfl_up1(ck.E[C - 1]);
+        const T v = (g.bc == 0) ? (T)(c.eR1 + (T)g.cm * (en1 - c.eR)) : (T)0;
+        uput<T, C>(ck.E, ir, lane == r.right / C, v);
+        c.eR = v;
+        c.eR1 = en1;
     }
 }
 
@@ -355,31 +419,94 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const 
 
 namespace fdtdp {
 
-// Role of this lane's chunk [k0, k0 + C) within grid b of n nodes.
-__device__ __forceinline__ ChunkRole chunk_role(const Grids &g, int b, int64_t n, int64_t k0,
-                                                int64_t wave_lo, int64_t wave_hi, int C)
-{
-    ChunkRole r;
-    const int64_t s = g.src[b];
-    r.src_any = s >= wave_lo && s < wave_hi;
-    r.isrc = (s >= k0 && s < k0 + C) ? (int)(s - k0) : -1;
-    r.left_any = wave_lo <= 0;
-    r.ileft = (k0 <= 0 && k0 + C > 0) ? (int)(-k0) : -1;
-    r.right_any = n - 1 >= wave_lo && n - 1 < wave_hi;
-    r.iright = (n - 1 >= k0 && n - 1 < k0 + C) ? (int)(n - 1 - k0) : -1;
-    return r;
-}
+// The probes a wave samples: those of grid b at nodes in [lo, hi) (inside
+// the wave's span).  The first two are kept as wave-uniform positions and
+// sample-row offsets; a wave with more walks the probe list every step.
+struct WaveProbes {
+    int n;               // probes in range
+    int pos[2];          // node position from the wave's first node
+    int64_t row[2];      // (b * P + p) * SB: the probe's row of the sample buffer
+};
 
-// Probe samples of the lane's chunk for one step.
-template <typename T, int C>
-__device__ __forceinline__ void chunk_probes(const Grids &g, int b, int64_t k0, int64_t out_lo,
-                                             int64_t out_hi, const T (&E)[C], int slot)
+__device__ __forceinline__ WaveProbes wave_probes_find(const Grids &g, int b, int64_t wave_lo, int64_t lo,
+                                                      int64_t hi)
 {
+    WaveProbes w;
+    w.n = 0;
+    w.pos[0] = w.pos[1] = 0;
+    w.row[0] = w.row[1] = 0;
     for (int p = 0; p < g.P; ++p) {
         const int64_t q = g.probe[(int64_t)b * g.P + p];
-        if (q >= out_lo && q < out_hi && q >= k0 && q < k0 + C)
-            g.samp[((int64_t)b * g.P + p) * g.SB + slot] = (double)pick<T, C>(E, (int)(q - k0));
+        if (q >= lo && q < hi) {
+            if (w.n < 2) {
+                w.pos[w.n] = uniform(q - wave_lo);
+                w.row[w.n] = ((int64_t)b * g.P + p) * g.SB;
+            }
+            ++w.n;
+        }
     }
+    w.n = uniform(w.n);
+    return w;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void wave_probe_store(const Grids &g, int pos, int64_t row, int lane,
+                                                 const T (&E)[C], int slot)
+{
+    const T v = upick<T, C>(E, pos % C);
+    if (lane == pos / C) g.samp[row + slot] = (double)v;
+}
+
+// Samples of one step (after the step's ends).
+template <typename T, int C>
+__device__ __forceinline__ void wave_probes(const Grids &g, const WaveProbes &w, int b, int64_t wave_lo,
+                                            int64_t lo, int64_t hi, int lane, const T (&E)[C], int slot)
+{
+    if (w.n <= 2) {
+        if (w.n > 0) wave_probe_store<T, C>(g, w.pos[0], w.row[0], lane, E, slot);
+        if (w.n > 1) wave_probe_store<T, C>(g, w.pos[1], w.row[1], lane, E, slot);
+        return;
+    }
+    for (int p = 0; p < g.P; ++p) {
+        const int64_t q = g.probe[(int64_t)b * g.P + p];
+        if (q >= lo && q < hi)
+            wave_probe_store<T, C>(g, uniform(q - wave_lo), ((int64_t)b * g.P + p) * g.SB, lane, E, slot);
+    }
+}
+
+// nsteps full steps of a wave that holds a grid end, the source or a probe
+// (sample slots slot0 .. slot0 + nsteps - 1 of the window).  The source values
+// come from the window's table, 64 steps at a time (one per lane), and are
+// broadcast from lane st % 64.
+template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
+__device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g, const WaveRole &r,
+                                         int lane, int b, int64_t wave_lo, int64_t plo, int64_t phi,
+                                         bool probes, int nsteps, int slot0, GetEr er, GetHl hl)
+{
+    EndCarry<T> c;
+    ends_init<T, C>(ck.E, r, c);
+    WaveProbes wp;
+    wp.n = 0;
+    if (probes) wp = wave_probes_find(g, b, wave_lo, plo, phi);
+    double svl = 0.0;
+    auto one = [&](int st) {
+        double sv = 0.0;
+        if (r.src >= 0) {
+            if ((st & 63) == 0) {
+                const int i = slot0 + st + lane;
+                svl = g.srcv[i < g.SB ? i : g.SB - 1];
+            }
+            sv = readlane_d(svl, st & 63);
+        }
+        chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
+        if (wp.n) wave_probes<T, C>(g, wp, b, wave_lo, plo, phi, lane, ck.E, slot0 + st);
+    };
+    int st = 0;
+    for (; st + 2 <= nsteps; st += 2) {
+        one(st);
+        one(st + 1);
+    }
+    if (st < nsteps) one(st);
 }
 
 // Block index remapped so that each XCD (workgroups are dealt round-robin to
@@ -394,7 +521,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk)
 
 template <typename T, int C, int KLASS>
 __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, const Tile *tiles,
-                                               int64_t ntiles, int nsteps, int64_t m0, int slot0)
+                                               int64_t ntiles, int nsteps, int slot0)
 {
     // class 0: vacuum tiles; 1: tiles with plasma; 2: tiles touching a CPML
     // layer (which may also hold plasma further in)
@@ -402,20 +529,19 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     constexpr bool CPML = KLASS == 2;
     const int lane = threadIdx.x & 63;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t t = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t t = blk * (blockDim.x >> 6) + uniform(threadIdx.x >> 6);
     if (t >= ntiles) return;
     const Tile tl = tiles[t];
     const int b = tl.grid;
     const int64_t off = g.off[b], n = g.n[b];
     const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
-    const int64_t wave_hi = (int64_t)tl.lo + 64LL * C;
     Chunk<T, C, PLASMA, CPML> ck;
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
-    ChunkRole role = chunk_role(g, b, n, k0, tl.lo, tl.hi, C);
+    const WaveRole role = wave_role(g, b, n, tl.lo, tl.hi);
     const bool probes = (tl.flags & TILE_PROBE) != 0;
     auto er = [](T e0) { return shfl_down1(e0); };
     auto hl = [](T h) { return shfl_up1(h); };
-    if (!(role.left_any || role.right_any || role.src_any || probes)) {
+    if (!has_role(role) && !probes) {
         // two steps per trip: the loop-carried E copies then alternate
         // registers instead of being moved back every step
         int st = 0;
@@ -425,12 +551,9 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
         }
         if (st < nsteps) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
     } else {
-        for (int st = 0; st < nsteps; ++st) {
-            chunk_step<T, C, PLASMA, CPML>(ck, g, role, m0 + st + 1, er, hl);
-            if (probes) chunk_probes<T, C>(g, b, k0, tl.out_lo, tl.out_hi, ck.E, slot0 + st);
-        }
+        run_role<T, C, PLASMA, CPML>(ck, g, role, lane, b, tl.lo, tl.out_lo, tl.out_hi, probes, nsteps, slot0,
+                                     er, hl);
     }
-    (void)wave_hi;
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
 
@@ -443,14 +566,14 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
 // in-wave move).
 template <typename T, int C, int KLASS, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int cur, const Tile *tiles,
-                                                       int64_t ntiles, int nsteps, int64_t m0, int slot0)
+                                                       int64_t ntiles, int nsteps, int slot0)
 {
     constexpr bool PLASMA = KLASS >= 1;
     constexpr bool CPML = KLASS == 2;
     __shared__ T ldsE[WAVES];
     __shared__ T ldsH[WAVES];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = uniform(threadIdx.x >> 6);
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
     if (t >= ntiles) return;                  // whole workgroup: no barrier is left waiting
     const Tile tl = tiles[t];
@@ -461,8 +584,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
     const int64_t k0 = wave_lo + (int64_t)lane * C;
     Chunk<T, C, PLASMA, CPML> ck;
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
-    ChunkRole role = chunk_role(g, b, n, k0, wave_lo, wave_hi > wave_lo ? wave_hi : wave_lo, C);
+    const WaveRole role = wave_role(g, b, n, wave_lo, wave_hi > wave_lo ? wave_hi : wave_lo);
     const bool probes = (tl.flags & TILE_PROBE) != 0;
+    // probes this wave samples: tile outputs inside the wave's span
+    const int64_t plo = tl.out_lo > wave_lo ? tl.out_lo : wave_lo;
+    const int64_t phi = tl.out_hi < wave_hi ? tl.out_hi : wave_hi;
     auto er = [&](T e0) {
         if (lane == 0) ldsE[w] = e0;
         __syncthreads();
@@ -477,78 +603,75 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
         if (lane == 0) v = (w > 0) ? ldsH[w - 1] : (T)0;
         return v;
     };
-    if (!(role.left_any || role.right_any || role.src_any || probes)) {
+    if (!has_role(role) && !(probes && plo < phi)) {
         for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
     } else {
-        for (int st = 0; st < nsteps; ++st) {
-            chunk_step<T, C, PLASMA, CPML>(ck, g, role, m0 + st + 1, er, hl);
-            if (probes) chunk_probes<T, C>(g, b, k0, tl.out_lo, tl.out_hi, ck.E, slot0 + st);
-        }
+        run_role<T, C, PLASMA, CPML>(ck, g, role, lane, b, wave_lo, plo, phi, probes, nsteps, slot0, er, hl);
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
 
 template <typename T, int C, int WAVES>
 void launch_tiledw_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
-                     int nsteps, int64_t m0, int slot0, hipStream_t st)
+                     int nsteps, int slot0, hipStream_t st)
 {
     const dim3 grid((unsigned)ntiles), blk(WAVES * 64);
     if (klass == 0)
-        hipLaunchKernelGGL((k_tiledw<T, C, 0, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps, m0,
+        hipLaunchKernelGGL((k_tiledw<T, C, 0, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
                            slot0);
     else if (klass == 1)
-        hipLaunchKernelGGL((k_tiledw<T, C, 1, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps, m0,
+        hipLaunchKernelGGL((k_tiledw<T, C, 1, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
                            slot0);
     else
-        hipLaunchKernelGGL((k_tiledw<T, C, 2, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps, m0,
+        hipLaunchKernelGGL((k_tiledw<T, C, 2, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
                            slot0);
 }
 
 template <typename T, int WAVES>
 void launch_tiledw_w(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
-                     int C, int nsteps, int64_t m0, int slot0, hipStream_t st)
+                     int C, int nsteps, int slot0, hipStream_t st)
 {
     switch (C) {
-    case 4: launch_tiledw_c<T, 4, WAVES>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
-    default: launch_tiledw_c<T, 8, WAVES>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
+    case 4: launch_tiledw_c<T, 4, WAVES>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
+    default: launch_tiledw_c<T, 8, WAVES>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
     }
 }
 
 template <typename T, int C>
 void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
-                    int klass, int nsteps, int64_t m0, int slot0, hipStream_t st)
+                    int klass, int nsteps, int slot0, hipStream_t st)
 {
     const unsigned nb = (unsigned)((ntiles + 3) / 4);
     if (klass == 0)
         hipLaunchKernelGGL((k_tiled<T, C, 0>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
-                           nsteps, m0, slot0);
+                           nsteps, slot0);
     else if (klass == 1)
         hipLaunchKernelGGL((k_tiled<T, C, 1>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
-                           nsteps, m0, slot0);
+                           nsteps, slot0);
     else
         hipLaunchKernelGGL((k_tiled<T, C, 2>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
-                           nsteps, m0, slot0);
+                           nsteps, slot0);
 }
 
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
-                  int C, int nsteps, int64_t m0, int slot0, hipStream_t st, int waves)
+                  int C, int nsteps, int slot0, hipStream_t st, int waves)
 {
-    if (waves == 2) return launch_tiledw_w<T, 2>(g, s, cur, tiles, ntiles, klass, C, nsteps, m0, slot0, st);
-    if (waves == 4) return launch_tiledw_w<T, 4>(g, s, cur, tiles, ntiles, klass, C, nsteps, m0, slot0, st);
-    if (waves == 8) return launch_tiledw_w<T, 8>(g, s, cur, tiles, ntiles, klass, C, nsteps, m0, slot0, st);
+    if (waves == 2) return launch_tiledw_w<T, 2>(g, s, cur, tiles, ntiles, klass, C, nsteps, slot0, st);
+    if (waves == 4) return launch_tiledw_w<T, 4>(g, s, cur, tiles, ntiles, klass, C, nsteps, slot0, st);
+    if (waves == 8) return launch_tiledw_w<T, 8>(g, s, cur, tiles, ntiles, klass, C, nsteps, slot0, st);
     switch (C) {
-    case 4: launch_tiled_c<T, 4>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
-    case 8: launch_tiled_c<T, 8>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
-    case 12: launch_tiled_c<T, 12>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
-    default: launch_tiled_c<T, 16>(g, s, cur, tiles, ntiles, klass, nsteps, m0, slot0, st); break;
+    case 4: launch_tiled_c<T, 4>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
+    case 8: launch_tiled_c<T, 8>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
+    case 12: launch_tiled_c<T, 12>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
+    default: launch_tiled_c<T, 16>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
     }
 }
 
 template void launch_tiled<float>(const Grids &, State<float> &, int, const Tile *, int64_t, int, int,
-                                  int, int64_t, int, hipStream_t, int);
+                                  int, int, hipStream_t, int);
 template void launch_tiled<double>(const Grids &, State<double> &, int, const Tile *, int64_t, int,
-                                   int, int, int64_t, int, hipStream_t, int);
+                                   int, int, int, hipStream_t, int);
 
 // ------------------------------------------------------------- resident
 
@@ -558,12 +681,12 @@ template void launch_tiled<double>(const Grids &, State<double> &, int, const Ti
 template <typename T, int C, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, int cur, int out,
                                                          const ResidentSlot *slots, int nsteps,
-                                                         int64_t m0, int slot0)
+                                                         int slot0)
 {
     __shared__ T ldsE[WAVES];
     __shared__ T ldsH[WAVES];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = uniform(threadIdx.x >> 6);
     const ResidentSlot sl = slots[(int64_t)blockIdx.x * WAVES + w];
     const bool active = sl.grid >= 0;
     const int b = active ? sl.grid : 0;
@@ -586,43 +709,40 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
         }
         ck.pmask = 0;
     }
-    ChunkRole role = active ? chunk_role(g, b, n, k0, wave_lo < 0 ? 0 : wave_lo, wave_hi, C)
-                            : ChunkRole{-1, -1, -1, false, false, false};
-    for (int st = 0; st < nsteps; ++st) {
-        auto get_er = [&](T e0) {
-            if (lane == 0) ldsE[w] = e0;
-            __syncthreads();
-            T v = shfl_down1(e0);
-            if (lane == 63) v = has_next ? ldsE[w + 1] : (T)0;
-            return v;
-        };
-        auto get_hl = [&](T hl) {
-            if (lane == 63) ldsH[w] = hl;
-            __syncthreads();
-            T v = shfl_up1(hl);
-            if (lane == 0) v = has_prev ? ldsH[w - 1] : (T)0;
-            return v;
-        };
-        chunk_step<T, C, true, false>(ck, g, role, m0 + st + 1, get_er, get_hl);
-        if (active) chunk_probes<T, C>(g, b, k0, wave_lo < 0 ? 0 : wave_lo, wave_hi, ck.E, slot0 + st);
-    }
+    const WaveRole role = active ? wave_role(g, b, n, wave_lo, wave_hi) : WaveRole{-1, -1, -1};
+    auto get_er = [&](T e0) {
+        if (lane == 0) ldsE[w] = e0;
+        __syncthreads();
+        T v = shfl_down1(e0);
+        if (lane == 63) v = has_next ? ldsE[w + 1] : (T)0;
+        return v;
+    };
+    auto get_hl = [&](T hl) {
+        if (lane == 63) ldsH[w] = hl;
+        __syncthreads();
+        T v = shfl_up1(hl);
+        if (lane == 0) v = has_prev ? ldsH[w - 1] : (T)0;
+        return v;
+    };
+    run_role<T, C, true, false>(ck, g, role, lane, b, wave_lo, wave_lo < 0 ? 0 : wave_lo, wave_hi, active,
+                                nsteps, slot0, get_er, get_hl);
     if (active) chunk_store<T, C, true, false>(ck, g, s, out, b, off, n, k0, 0, n);
 }
 
 template <typename T>
 void launch_resident(const Grids &g, State<T> &s, int cur, int out, const ResidentSlot *slots, int64_t nbins,
-                     int waves_per_wg, int C, int nsteps, int64_t m0, int slot0, hipStream_t st)
+                     int waves_per_wg, int C, int nsteps, int slot0, hipStream_t st)
 {
     (void)C;
     (void)waves_per_wg;   // 8 waves: 512 threads keep the per-node coefficients in VGPRs
     hipLaunchKernelGGL((k_resident<T, 8, 8>), dim3((unsigned)nbins), dim3(8 * 64), 0, st, g, s,
-                       cur, out, slots, nsteps, m0, slot0);
+                       cur, out, slots, nsteps, slot0);
 }
 
 template void launch_resident<float>(const Grids &, State<float> &, int, int, const ResidentSlot *, int64_t,
-                                     int, int, int, int64_t, int, hipStream_t);
+                                     int, int, int, int, hipStream_t);
 template void launch_resident<double>(const Grids &, State<double> &, int, int, const ResidentSlot *,
-                                      int64_t, int, int, int, int64_t, int, hipStream_t);
+                                      int64_t, int, int, int, int, hipStream_t);
 
 int resident_max_nodes(int C, int waves) { return 64 * C * waves; }
 

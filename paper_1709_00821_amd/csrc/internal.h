@@ -29,6 +29,7 @@ struct Grids {
     double cm;              // Mur coefficient (S-1)/(S+1)
     double src_tau, src_t0, src_amp;
     const double *cpml;     // [4][cpmlP]: bE(depth d+1), aE(d+1), bH(depth j+1/2), aH(j+1/2)
+    const double *srcv;     // [SB] eq.(15) source value of every step of the current window
 };
 
 // State buffers of one precision.
@@ -86,19 +87,20 @@ void launch_step(const Grids &g, State<T> &s, int cur, int64_t total_nodes, int6
 // 8: one workgroup a tile, neighbouring waves through LDS).
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
-                  int klass, int C, int nsteps, int64_t m0, int slot0, hipStream_t st, int waves = 1);
+                  int klass, int C, int nsteps, int slot0, hipStream_t st, int waves = 1);
 
 // Reads buffer cur, writes buffer out (cur itself for a whole-run resident
 // call, the other buffer when bins and tiles share a pass).
 template <typename T>
 void launch_resident(const Grids &g, State<T> &s, int cur, int out, const ResidentSlot *slots,
-                     int64_t nbins, int waves_per_wg, int C, int nsteps, int64_t m0,
-                     int slot0, hipStream_t st);
+                     int64_t nbins, int waves_per_wg, int C, int nsteps, int slot0, hipStream_t st);
 
 void launch_dft(const Grids &g, const double *freqs, int F, int64_t m_first, int count,
                 double2 *tw, double2 *X, int64_t rows, hipStream_t st);
 
 void launch_fill(void *p, int64_t bytes, hipStream_t st);
+// srcv[i] = source value of step m_first + i, i < count (eq.(15) at t = m dt)
+void launch_src_table(const Grids &g, int64_t m_first, int count, double *srcv, hipStream_t st);
 
 void launch_cpml_table(double *tab, int P, double m, double smax, double dt, hipStream_t st);
 

@@ -243,6 +243,20 @@ void launch_fill(void *p, int64_t bytes, hipStream_t st)
     hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, st, (uint4 *)p, n16);
 }
 
+__global__ void k_src_table(Grids g, int64_t m_first, int count, double *srcv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    srcv[i] = source_value((double)(m_first + i) * g.dt, g.src_tau, g.src_t0, g.src_amp);
+}
+
+void launch_src_table(const Grids &g, int64_t m_first, int count, double *srcv, hipStream_t st)
+{
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_src_table, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, g, m_first, count,
+                       srcv);
+}
+
 __global__ void k_cpml_table(double *tab, int P, double m, double smax, double dt)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
