@@ -457,16 +457,12 @@ __device__ __forceinline__ void wave_probe_store(const Grids &g, int pos, int64_
     if (lane == pos / C) g.samp[row + slot] = (double)v;
 }
 
-// Samples of one step (after the step's ends).
+// Samples of one step (after the step's ends), one store per probe: the
+// path for a wave that holds more than two probes.
 template <typename T, int C>
-__device__ __forceinline__ void wave_probes(const Grids &g, const WaveProbes &w, int b, int64_t wave_lo,
-                                            int64_t lo, int64_t hi, int lane, const T (&E)[C], int slot)
+__device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_lo, int64_t lo, int64_t hi,
+                                            int lane, const T (&E)[C], int slot)
 {
-    if (w.n <= 2) {
-        if (w.n > 0) wave_probe_store<T, C>(g, w.pos[0], w.row[0], lane, E, slot);
-        if (w.n > 1) wave_probe_store<T, C>(g, w.pos[1], w.row[1], lane, E, slot);
-        return;
-    }
     for (int p = 0; p < g.P; ++p) {
         const int64_t q = g.probe[(int64_t)b * g.P + p];
         if (q >= lo && q < hi)
@@ -475,9 +471,12 @@ __device__ __forceinline__ void wave_probes(const Grids &g, const WaveProbes &w,
 }
 
 // nsteps full steps of a wave that holds a grid end, the source or a probe
-// (sample slots slot0 .. slot0 + nsteps - 1 of the window).  The source values
-// come from the window's table, 64 steps at a time (one per lane), and are
-// broadcast from lane st % 64.
+// (sample slots slot0 .. slot0 + nsteps - 1 of the window), in runs of up to
+// 64 steps.  The only load is at the start of a run: the source values of its
+// steps, one per lane of the window's table, broadcast from lane st.  Inside a
+// run the wave issues nothing but the probe stores, which it never waits on.
+// (Every cross-lane read here takes a value all lanes computed: a value
+// computed only in some lanes would be stale in the lane that is read.)
 template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
 __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g, const WaveRole &r,
                                          int lane, int b, int64_t wave_lo, int64_t plo, int64_t phi,
@@ -488,25 +487,31 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Gr
     WaveProbes wp;
     wp.n = 0;
     if (probes) wp = wave_probes_find(g, b, wave_lo, plo, phi);
-    double svl = 0.0;
-    auto one = [&](int st) {
-        double sv = 0.0;
+    for (int base = 0; base < nsteps; base += 64) {
+        const int cnt = nsteps - base < 64 ? nsteps - base : 64;
+        const int slot = slot0 + base;
+        double svl = 0.0;
         if (r.src >= 0) {
-            if ((st & 63) == 0) {
-                const int i = slot0 + st + lane;
-                svl = g.srcv[i < g.SB ? i : g.SB - 1];
-            }
-            sv = readlane_d(svl, st & 63);
+            const int i = slot + lane;
+            svl = g.srcv[i < g.SB ? i : g.SB - 1];
         }
-        chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
-        if (wp.n) wave_probes<T, C>(g, wp, b, wave_lo, plo, phi, lane, ck.E, slot0 + st);
-    };
-    int st = 0;
-    for (; st + 2 <= nsteps; st += 2) {
-        one(st);
-        one(st + 1);
+        auto one = [&](int st) {
+            const double sv = (r.src >= 0) ? readlane_d(svl, st) : 0.0;
+            chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
+            if (wp.n > 2) {
+                wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
+            } else {
+                if (wp.n > 0) wave_probe_store<T, C>(g, wp.pos[0], wp.row[0], lane, ck.E, slot + st);
+                if (wp.n > 1) wave_probe_store<T, C>(g, wp.pos[1], wp.row[1], lane, ck.E, slot + st);
+            }
+        };
+        int st = 0;
+        for (; st + 2 <= cnt; st += 2) {
+            one(st);
+            one(st + 1);
+        }
+        if (st < cnt) one(st);
     }
-    if (st < nsteps) one(st);
 }
 
 // Block index remapped so that each XCD (workgroups are dealt round-robin to
