@@ -73,7 +73,7 @@ def roofline(prof, precision):
     """Dominant kernel: achieved = algorithmic bytes per launch (bytes per node
     x nodes the launch advances, as the library reports) / mean launch time."""
     name, (ms_tot, calls, units) = max(prof.items(), key=lambda kv: kv[1][0])
-    per = algorithmic_bytes_per_node(precision, name in ("tiled_plasma", "tiled_cpml", "resident",
+    per = algorithmic_bytes_per_node(precision, name in ("tiled_plasma", "tiled_cpml", "tiled_role", "resident",
                                                          "step_h_e"))
     bytes_per_launch = per * units / calls
     avg_s = ms_tot / calls / 1e3
@@ -99,7 +99,7 @@ def alu_roofline(prof, kernel, steps_per_launch):
     ceiling is VALU issue: achieved = algorithmic flops of the node-updates a
     launch delivers / mean launch time."""
     ms_tot, calls, units = prof[kernel]
-    per = FLOPS_PLASMA if kernel in ("tiled_plasma", "tiled_cpml") else FLOPS_VAC
+    per = FLOPS_PLASMA if kernel in ("tiled_plasma", "tiled_cpml", "tiled_role") else FLOPS_VAC
     flops = per * units / calls * steps_per_launch
     avg_s = ms_tot / calls / 1e3
     ach = flops / avg_s / 1e12

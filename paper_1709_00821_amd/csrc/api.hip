@@ -92,8 +92,8 @@ struct fdtd_plasma {
     // tiled executor
     std::vector<Tile> tiles_host;
     Tile *d_tiles = nullptr;
-    int64_t ntiles[3] = {0, 0, 0};
-    int64_t tile_first[3] = {0, 0, 0};
+    int64_t ntiles[kTileClasses] = {0, 0, 0, 0};
+    int64_t tile_first[kTileClasses] = {0, 0, 0, 0};
     int tileC = 8, Kh = 16, tileW = 1;
 
     // resident executor
@@ -139,7 +139,7 @@ struct fdtd_plasma {
         hipEvent_t a, b;
         int64_t units;        // output nodes the launch group advances
     };
-    int64_t class_nodes[4] = {0, 0, 0, 0};   // output nodes per tile class; [3]: binned grids
+    int64_t class_nodes[kTileClasses + 1] = {0, 0, 0, 0, 0};   // output nodes per tile class; last: binned grids
     int64_t real_nodes = 0;
     bool profiling = false;
     std::vector<ProfMark> marks;
@@ -281,7 +281,7 @@ struct Plan {
     int SB = 0;
     std::vector<int64_t> off;
     std::vector<Tile> tiles;
-    int64_t ntiles[3] = {0, 0, 0}, tile_first[3] = {0, 0, 0};
+    int64_t ntiles[kTileClasses] = {0, 0, 0, 0}, tile_first[kTileClasses] = {0, 0, 0, 0};
     std::vector<ResidentSlot> slots;
     int64_t nbins = 0;
     int exec = 0, tileC = 8, Kh = 16, tileW = 1, resC = 8, resWaves = 8;
@@ -295,7 +295,7 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
     const int wave_nodes = p.tileC * 64;
     const int L = p.tileW * wave_nodes;
     const int W = L - 2 * p.Kh;
-    std::vector<Tile> cls[3];
+    std::vector<Tile> cls[kTileClasses];
     int64_t o = 0;
     for (int64_t b = 0; b < d->batch; ++b) {
         const int64_t n = d->cells[b];
@@ -325,13 +325,14 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
                 (t.lo < d->cpml_cells + 1 || t.hi > n - 2 - d->cpml_cells))
                 fl |= TILE_CPML;
             t.flags = fl;
-            const int k = (fl & TILE_CPML) ? 2 : (fl & TILE_PLASMA) ? 1 : 0;
+            const bool role = (fl & (TILE_LEFT_END | TILE_RIGHT_END | TILE_SOURCE | TILE_PROBE)) != 0;
+            const int k = (fl & TILE_CPML) ? 2 : role ? 3 : (fl & TILE_PLASMA) ? 1 : 0;
             cls[k].push_back(t);
         }
         o += n;
     }
     p.tiles.clear();
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kTileClasses; ++k) {
         p.tile_first[k] = (int64_t)p.tiles.size();
         p.ntiles[k] = (int64_t)cls[k].size();
         p.tiles.insert(p.tiles.end(), cls[k].begin(), cls[k].end());
@@ -578,7 +579,8 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
             room = std::min<int64_t>(room, h->ck_s - h->steps % h->ck_s);
         }
         int64_t k;
-        static const char *kTiledNames[3] = {"tiled_vacuum", "tiled_plasma", "tiled_cpml"};
+        static const char *kTiledNames[kTileClasses] = {"tiled_vacuum", "tiled_plasma", "tiled_cpml",
+                                                        "tiled_role"};
         if (h->exec == FDTD_EXEC_STEP) {
             k = 1;
             prof_begin(h, "step_h_e", h->real_nodes);
@@ -586,18 +588,22 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
             prof_end(h);
         } else if (h->exec == FDTD_EXEC_TILED) {
             k = std::min<int64_t>(std::min<int64_t>(left, room), h->Kh);
-            // the CPML class (a handful of tiles at the grid ends) runs beside
-            // the bulk classes: all classes of a pass write disjoint nodes
-            const bool fork = h->side && h->ntiles[2] && !h->profiling;
+            // the CPML and role classes (the tiles holding grid ends, sources
+            // and probes) run beside the bulk classes on the side stream: all
+            // classes of a pass write disjoint nodes
+            const bool fork = h->side && (h->ntiles[2] || h->ntiles[3]) && !h->profiling;
+            auto on_side = [&](int c) { return fork && c >= 2; };
             if (fork) {
                 (void)hipEventRecord(h->ev_fork, h->stream);
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-                launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[2], h->ntiles[2], 2,
-                                h->tileC, (int)k, slot, h->side, h->tileW);
+                for (int c = 2; c < kTileClasses; ++c)
+                    if (h->ntiles[c])
+                        launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC,
+                                        (int)k, slot, h->side, h->tileW);
                 (void)hipEventRecord(h->ev_join, h->side);
             }
-            for (int c = 0; c < 3; ++c)
-                if (h->ntiles[c] && !(fork && c == 2)) {
+            for (int c = 0; c < kTileClasses; ++c)
+                if (h->ntiles[c] && !on_side(c)) {
                     prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                     launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c,
                                     h->tileC, (int)k, slot, h->stream, h->tileW);
@@ -617,7 +623,7 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                 (void)hipEventRecord(h->ev_fork, h->stream);
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
             }
-            prof_begin(h, "resident", h->class_nodes[3]);
+            prof_begin(h, "resident", h->class_nodes[kTileClasses]);
             launch_resident<T>(g, s, h->cur, out, h->d_slots, h->nbins, h->resWaves, h->resC, (int)k, slot,
                                rs);
             prof_end(h);
@@ -625,7 +631,7 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
             int cur = h->cur;
             for (int64_t done = 0; done < k; done += h->Kh) {
                 const int kk = (int)std::min<int64_t>(h->Kh, k - done);
-                for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < kTileClasses; ++c)
                     if (h->ntiles[c]) {
                         prof_begin(h, kTiledNames[c], h->class_nodes[c]);
                         launch_tiled<T>(g, s, cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC, kk,
@@ -714,7 +720,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     h->resC = p.resC;
     h->resWaves = p.resWaves;
     h->nbins = p.nbins;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kTileClasses; ++k) {
         h->ntiles[k] = p.ntiles[k];
         h->tile_first[k] = p.tile_first[k];
         for (int64_t t = 0; t < p.ntiles[k]; ++t) {
@@ -728,7 +734,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         for (auto &sl : p.slots)
             if (sl.grid >= 0) binned[sl.grid] = 1;
         for (int64_t b = 0; b < desc->batch; ++b)
-            if (binned[b]) h->class_nodes[3] += desc->cells[b];
+            if (binned[b]) h->class_nodes[kTileClasses] += desc->cells[b];
     }
     h->cells.assign(desc->cells, desc->cells + desc->batch);
     h->off = p.off;
@@ -834,7 +840,8 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
                                                      : 0.8 * (m + 1.0) / (eta0 * desc->dz);
         launch_cpml_table(h->d_cpml, desc->cpml_cells, m, smax, desc->dt, st);
     }
-    if (((h->exec == FDTD_EXEC_TILED && h->ntiles[2] > 0) || h->exec == FDTD_EXEC_MIXED) && h->stream != nullptr) {
+    if (((h->exec == FDTD_EXEC_TILED && (h->ntiles[2] > 0 || h->ntiles[3] > 0)) || h->exec == FDTD_EXEC_MIXED) &&
+        h->stream != nullptr) {
         // default priority (no priority streams), non-blocking w.r.t. the null stream
         if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||

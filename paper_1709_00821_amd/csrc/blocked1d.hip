@@ -302,31 +302,40 @@ __device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, 
     chunk_j<T, C, PLASMA, CPML>(ck);
 }
 
-// Where a grid's special nodes sit in one wave's span of 64*C nodes, as
-// positions counted from the wave's first node (lane pos / C, register
-// pos % C); -1 when the wave does not hold the node.  The values are the same
-// in every lane (read through readfirstlane), so the register selects below
-// run on scalar conditions and the branches on them are scalar.
+// Where a grid's special nodes sit in one wave's span of 64*C nodes: a
+// node at position pos from the wave's first node is register pos % C of
+// lane pos / C.  The values are the same in every lane (read through
+// readfirstlane), so the register selects below run on scalar conditions.
+// A lane of -1 means the wave does not hold the node.
 struct WaveRole {
-    int left;    // node 0: 0 or 1 (a wave never starts left of node -1)
-    int right;   // node n-1: never register 0 of lane 0 (see the tile builder)
-    int src;     // the source node
+    int src_lane, src_reg;       // the source node
+    int left_lane, left_reg;     // node 0: lane 0, register 0 or 1 (a wave never starts left of node -1)
+    int right_lane, right_reg;   // node n-1: never register 0 of lane 0 (see the tile builder)
 };
 
 __device__ __forceinline__ int uniform(int64_t v) { return __builtin_amdgcn_readfirstlane((int)v); }
 
-__device__ __forceinline__ WaveRole wave_role(const Grids &g, int b, int64_t n, int64_t wave_lo,
-                                              int64_t wave_hi)
+template <int C>
+__device__ __forceinline__ WaveRole wave_role(const Grids &g, int b, int64_t n, int64_t wave_lo, int64_t wave_hi)
 {
-    WaveRole r;
-    r.left = uniform((wave_lo <= 0 && 0 < wave_hi) ? -wave_lo : -1);
-    r.right = uniform((n - 1 >= wave_lo && n - 1 < wave_hi) ? n - 1 - wave_lo : -1);
     const int64_t s = g.src[b];
-    r.src = uniform((s >= 0 && s >= wave_lo && s < wave_hi) ? s - wave_lo : -1);
+    const int64_t ps = (s >= 0 && s >= wave_lo && s < wave_hi) ? s - wave_lo : -1;
+    const int64_t pl = (wave_lo <= 0 && 0 < wave_hi) ? -wave_lo : -1;
+    const int64_t pr = (n - 1 >= wave_lo && n - 1 < wave_hi) ? n - 1 - wave_lo : -1;
+    WaveRole r;
+    r.src_lane = uniform(ps >= 0 ? ps / C : -1);
+    r.src_reg = uniform(ps >= 0 ? ps % C : 0);
+    r.left_lane = uniform(pl >= 0 ? 0 : -1);
+    r.left_reg = uniform(pl >= 0 ? pl : 0);
+    r.right_lane = uniform(pr >= 0 ? pr / C : -1);
+    r.right_reg = uniform(pr >= 0 ? pr % C : 1);
     return r;
 }
 
-__device__ __forceinline__ bool has_role(const WaveRole &r) { return r.left >= 0 || r.right >= 0 || r.src >= 0; }
+__device__ __forceinline__ bool has_role(const WaveRole &r)
+{
+    return r.src_lane >= 0 || r.left_lane >= 0 || r.right_lane >= 0;
+}
 
 // v[i] for a wave-uniform i in [0, C).  The registers are gathered into one
 // vector value and indexed there, which gfx950 code generation turns into
@@ -370,21 +379,19 @@ struct EndCarry {
 template <typename T, int C>
 __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, EndCarry<T> &c)
 {
-    c.e0 = c.e1 = c.eR = c.eR1 = (T)0;
-    if (r.left >= 0) {
-        c.e0 = r.left ? E[1] : E[0];
-        c.e1 = r.left ? E[2] : E[1];
-    }
-    if (r.right >= 0) {
-        const int ir = r.right % C;
-        c.eR = upick<T, C>(E, ir);
-        c.eR1 = ir ? upick<T, C>(E, ir - 1) : shfl_up1(E[C - 1]);
-    }
+    c.e0 = r.left_reg ? E[1] : E[0];
+    c.e1 = r.left_reg ? E[2] : E[1];
+    const int ir = r.right_reg;
+    c.eR = upick<T, C>(E, ir);
+    c.eR1 = ir ? upick<T, C>(E, ir - 1) : shfl_up1(E[C - 1]);
 }
 
-// One full time step of a wave holding a grid end or the source: H, E, the
-// source (added to E^{n+1}, eq.(15), before the J update), J, then the ends
-// (first-order Mur, or PEC E = 0).  sv: the source value of this step.
+// One full time step of a wave holding a grid end, the source or a probe: H,
+// E, the source (added to E^{n+1}, eq.(15), before the J update), J, then the
+// ends (first-order Mur, or PEC E = 0).  sv: the source value of this step.
+// Every part runs in every such wave, as selects whose lane condition is
+// false where the wave does not hold the node: no branch, so the registers
+// need no merging copies.
 template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
 __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
                                            const WaveRole &r, int lane, EndCarry<T> &c, double sv,
@@ -392,24 +399,25 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const 
 {
     chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
     chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
-    if (r.src >= 0) {
-        const int is = r.src % C;
-        uput<T, C>(ck.E, is, lane == r.src / C, add_source<T>(upick<T, C>(ck.E, is), sv));
-    }
+    uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
     chunk_j<T, C, PLASMA, CPML>(ck);
-    if (r.left >= 0) {
-        const T en1 = r.left ? ck.E[2] : ck.E[1];
-        const T v = (g.bc == 0) ? (T)(c.e1 + (T)g.cm * (en1 - c.e0)) : (T)0;
-        if (r.left) ck.E[1] = (lane == 0) ? v : ck.E[1];
-        else ck.E[0] = (lane == 0) ? v : ck.E[0];
+    const bool mur = g.bc == 0;
+    {
+        const T en1 = r.left_reg ? ck.E[2] : ck.E[1];
+        const T v = mur ? (T)(c.e1 + (T)g.cm * (en1 - c.e0)) : (T)0;
+        const bool here = lane == r.left_lane;
+        ck.E[0] = (here && !r.left_reg) ? v : ck.E[0];
+        ck.E[1] = (here && r.left_reg) ? v : ck.E[1];
         c.e0 = v;
         c.e1 = en1;
     }
-    if (r.right >= 0) {
-        const int ir = r.right % C;
-        const T en1 = ir ? upick<T, C>(ck.E, ir - 1) : shfl_up1(ck.E[C - 1]);
-        const T v = (g.bc == 0) ? (T)(c.eR1 + (T)g.cm * (en1 - c.eR)) : (T)0;
-        uput<T, C>(ck.E, ir, lane == r.right / C, v);
+    {
+        const int ir = r.right_reg;
+        const T prev = shfl_up1(ck.E[C - 1]);
+        const T left1 = upick<T, C>(ck.E, ir > 0 ? ir - 1 : 0);
+        const T en1 = ir > 0 ? left1 : prev;
+        const T v = mur ? (T)(c.eR1 + (T)g.cm * (en1 - c.eR)) : (T)0;
+        uput<T, C>(ck.E, ir, lane == r.right_lane, v);
         c.eR = v;
         c.eR1 = en1;
     }
@@ -420,41 +428,48 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const 
 namespace fdtdp {
 
 // The probes a wave samples: those of grid b at nodes in [lo, hi) (inside
-// the wave's span).  The first two are kept as wave-uniform positions and
-// sample-row offsets; a wave with more walks the probe list every step.
+// the wave's span).  The first two are kept as wave-uniform lane, register
+// and sample-row offset; a wave with more walks the probe list every step.
 struct WaveProbes {
-    int n;               // probes in range
-    int pos[2];          // node position from the wave's first node
-    int64_t row[2];      // (b * P + p) * SB: the probe's row of the sample buffer
+    int n;                 // probes in range
+    int lane[2], reg[2];   // where the probe node sits in the wave
+    int64_t row[2];        // (b * P + p) * SB: the probe's row of the sample buffer
 };
 
+template <int C>
 __device__ __forceinline__ WaveProbes wave_probes_find(const Grids &g, int b, int64_t wave_lo, int64_t lo,
                                                       int64_t hi)
 {
-    WaveProbes w;
-    w.n = 0;
-    w.pos[0] = w.pos[1] = 0;
-    w.row[0] = w.row[1] = 0;
+    int n = 0;
+    int64_t q0 = 0, q1 = 0, r0 = 0, r1 = 0;
     for (int p = 0; p < g.P; ++p) {
         const int64_t q = g.probe[(int64_t)b * g.P + p];
         if (q >= lo && q < hi) {
-            if (w.n < 2) {
-                w.pos[w.n] = uniform(q - wave_lo);
-                w.row[w.n] = ((int64_t)b * g.P + p) * g.SB;
-            }
-            ++w.n;
+            const int64_t row = ((int64_t)b * g.P + p) * g.SB;
+            if (n == 0) { q0 = q - wave_lo; r0 = row; }
+            if (n == 1) { q1 = q - wave_lo; r1 = row; }
+            ++n;
         }
     }
-    w.n = uniform(w.n);
+    WaveProbes w;
+    w.n = uniform(n);
+    w.lane[0] = uniform(q0 / C);
+    w.reg[0] = uniform(q0 % C);
+    w.lane[1] = uniform(q1 / C);
+    w.reg[1] = uniform(q1 % C);
+    w.row[0] = (int64_t)__builtin_amdgcn_readfirstlane((int)r0) |
+               ((int64_t)__builtin_amdgcn_readfirstlane((int)(r0 >> 32)) << 32);
+    w.row[1] = (int64_t)__builtin_amdgcn_readfirstlane((int)r1) |
+               ((int64_t)__builtin_amdgcn_readfirstlane((int)(r1 >> 32)) << 32);
     return w;
 }
 
 template <typename T, int C>
-__device__ __forceinline__ void wave_probe_store(const Grids &g, int pos, int64_t row, int lane,
+__device__ __forceinline__ void wave_probe_store(const Grids &g, int lane_p, int reg, int64_t row, int lane,
                                                  const T (&E)[C], int slot)
 {
-    const T v = upick<T, C>(E, pos % C);
-    if (lane == pos / C) g.samp[row + slot] = (double)v;
+    const T v = upick<T, C>(E, reg);
+    if (lane == lane_p) g.samp[row + slot] = (double)v;
 }
 
 // Samples of one step (after the step's ends), one store per probe: the
@@ -465,8 +480,10 @@ __device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_
 {
     for (int p = 0; p < g.P; ++p) {
         const int64_t q = g.probe[(int64_t)b * g.P + p];
-        if (q >= lo && q < hi)
-            wave_probe_store<T, C>(g, uniform(q - wave_lo), ((int64_t)b * g.P + p) * g.SB, lane, E, slot);
+        if (q >= lo && q < hi) {
+            const int pos = uniform(q - wave_lo);
+            wave_probe_store<T, C>(g, pos / C, pos % C, ((int64_t)b * g.P + p) * g.SB, lane, E, slot);
+        }
     }
 }
 
@@ -479,30 +496,27 @@ __device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_
 // computed only in some lanes would be stale in the lane that is read.)
 template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
 __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g, const WaveRole &r,
-                                         int lane, int b, int64_t wave_lo, int64_t plo, int64_t phi,
-                                         bool probes, int nsteps, int slot0, GetEr er, GetHl hl)
+                                         const WaveProbes &wp, int lane, int b, int64_t wave_lo, int64_t plo,
+                                         int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl)
 {
     EndCarry<T> c;
     ends_init<T, C>(ck.E, r, c);
-    WaveProbes wp;
-    wp.n = 0;
-    if (probes) wp = wave_probes_find(g, b, wave_lo, plo, phi);
     for (int base = 0; base < nsteps; base += 64) {
         const int cnt = nsteps - base < 64 ? nsteps - base : 64;
         const int slot = slot0 + base;
         double svl = 0.0;
-        if (r.src >= 0) {
+        if (r.src_lane >= 0) {
             const int i = slot + lane;
             svl = g.srcv[i < g.SB ? i : g.SB - 1];
         }
         auto one = [&](int st) {
-            const double sv = (r.src >= 0) ? readlane_d(svl, st) : 0.0;
+            const double sv = (r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
             chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
             if (wp.n > 2) {
                 wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
             } else {
-                if (wp.n > 0) wave_probe_store<T, C>(g, wp.pos[0], wp.row[0], lane, ck.E, slot + st);
-                if (wp.n > 1) wave_probe_store<T, C>(g, wp.pos[1], wp.row[1], lane, ck.E, slot + st);
+                if (wp.n > 0) wave_probe_store<T, C>(g, wp.lane[0], wp.reg[0], wp.row[0], lane, ck.E, slot + st);
+                if (wp.n > 1) wave_probe_store<T, C>(g, wp.lane[1], wp.reg[1], wp.row[1], lane, ck.E, slot + st);
             }
         };
         int st = 0;
@@ -524,12 +538,14 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk)
     return x * q + (x < r ? x : r) + j;
 }
 
-template <typename T, int C, int KLASS>
+template <typename T, int C, int KLASS, bool ROLES>
 __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, const Tile *tiles,
                                                int64_t ntiles, int nsteps, int slot0)
 {
     // class 0: vacuum tiles; 1: tiles with plasma; 2: tiles touching a CPML
-    // layer (which may also hold plasma further in)
+    // layer (which may also hold plasma further in).  ROLES: the tiles hold a
+    // grid end, the source or a probe (a separate instantiation, so that the
+    // bulk tiles' register budget is that of the plain step alone)
     constexpr bool PLASMA = KLASS >= 1;
     constexpr bool CPML = KLASS == 2;
     const int lane = threadIdx.x & 63;
@@ -542,11 +558,9 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
     Chunk<T, C, PLASMA, CPML> ck;
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
-    const WaveRole role = wave_role(g, b, n, tl.lo, tl.hi);
-    const bool probes = (tl.flags & TILE_PROBE) != 0;
     auto er = [](T e0) { return shfl_down1(e0); };
     auto hl = [](T h) { return shfl_up1(h); };
-    if (!has_role(role) && !probes) {
+    if constexpr (!ROLES) {
         // two steps per trip: the loop-carried E copies then alternate
         // registers instead of being moved back every step
         int st = 0;
@@ -556,8 +570,12 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
         }
         if (st < nsteps) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
     } else {
-        run_role<T, C, PLASMA, CPML>(ck, g, role, lane, b, tl.lo, tl.out_lo, tl.out_hi, probes, nsteps, slot0,
-                                     er, hl);
+        const WaveRole role = wave_role<C>(g, b, n, tl.lo, tl.hi);
+        WaveProbes wp;
+        wp.n = 0;
+        if (tl.flags & TILE_PROBE) wp = wave_probes_find<C>(g, b, tl.lo, tl.out_lo, tl.out_hi);
+        run_role<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0, er,
+                                     hl);
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
@@ -589,7 +607,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
     const int64_t k0 = wave_lo + (int64_t)lane * C;
     Chunk<T, C, PLASMA, CPML> ck;
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
-    const WaveRole role = wave_role(g, b, n, wave_lo, wave_hi > wave_lo ? wave_hi : wave_lo);
+    const WaveRole role = wave_role<C>(g, b, n, wave_lo, wave_hi > wave_lo ? wave_hi : wave_lo);
     const bool probes = (tl.flags & TILE_PROBE) != 0;
     // probes this wave samples: tile outputs inside the wave's span
     const int64_t plo = tl.out_lo > wave_lo ? tl.out_lo : wave_lo;
@@ -608,10 +626,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
         if (lane == 0) v = (w > 0) ? ldsH[w - 1] : (T)0;
         return v;
     };
-    if (!has_role(role) && !(probes && plo < phi)) {
+    WaveProbes wp;
+    wp.n = 0;
+    if (probes && plo < phi) wp = wave_probes_find<C>(g, b, wave_lo, plo, phi);
+    if (!has_role(role) && wp.n == 0) {
         for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
     } else {
-        run_role<T, C, PLASMA, CPML>(ck, g, role, lane, b, wave_lo, plo, phi, probes, nsteps, slot0, er, hl);
+        run_role<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, wave_lo, plo, phi, nsteps, slot0, er, hl);
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
@@ -621,14 +642,15 @@ void launch_tiledw_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, in
                      int nsteps, int slot0, hipStream_t st)
 {
     const dim3 grid((unsigned)ntiles), blk(WAVES * 64);
+    // class 3 (role tiles) takes the plasma kernel, which holds both paths
     if (klass == 0)
         hipLaunchKernelGGL((k_tiledw<T, C, 0, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
                            slot0);
-    else if (klass == 1)
-        hipLaunchKernelGGL((k_tiledw<T, C, 1, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
+    else if (klass == 2)
+        hipLaunchKernelGGL((k_tiledw<T, C, 2, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
                            slot0);
     else
-        hipLaunchKernelGGL((k_tiledw<T, C, 2, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
+        hipLaunchKernelGGL((k_tiledw<T, C, 1, WAVES>), grid, blk, 0, st, g, s, cur, tiles, ntiles, nsteps,
                            slot0);
 }
 
@@ -648,13 +670,16 @@ void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int
 {
     const unsigned nb = (unsigned)((ntiles + 3) / 4);
     if (klass == 0)
-        hipLaunchKernelGGL((k_tiled<T, C, 0>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
+        hipLaunchKernelGGL((k_tiled<T, C, 0, false>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
                            nsteps, slot0);
     else if (klass == 1)
-        hipLaunchKernelGGL((k_tiled<T, C, 1>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
+        hipLaunchKernelGGL((k_tiled<T, C, 1, false>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
                            nsteps, slot0);
-    else
-        hipLaunchKernelGGL((k_tiled<T, C, 2>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
+    else if (klass == 2)
+        hipLaunchKernelGGL((k_tiled<T, C, 2, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
+                           nsteps, slot0);
+    else   // role tiles, vacuum or plasma: the plasma step reproduces the vacuum one
+        hipLaunchKernelGGL((k_tiled<T, C, 1, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
                            nsteps, slot0);
 }
 
@@ -714,7 +739,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
         }
         ck.pmask = 0;
     }
-    const WaveRole role = active ? wave_role(g, b, n, wave_lo, wave_hi) : WaveRole{-1, -1, -1};
+    const WaveRole role = active ? wave_role<C>(g, b, n, wave_lo, wave_hi) : WaveRole{-1, 0, -1, 0, -1, 1};
     auto get_er = [&](T e0) {
         if (lane == 0) ldsE[w] = e0;
         __syncthreads();
@@ -729,8 +754,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
         if (lane == 0) v = has_prev ? ldsH[w - 1] : (T)0;
         return v;
     };
-    run_role<T, C, true, false>(ck, g, role, lane, b, wave_lo, wave_lo < 0 ? 0 : wave_lo, wave_hi, active,
-                                nsteps, slot0, get_er, get_hl);
+    const int64_t plo = wave_lo < 0 ? 0 : wave_lo;
+    WaveProbes wp;
+    wp.n = 0;
+    if (active) wp = wave_probes_find<C>(g, b, wave_lo, plo, wave_hi);
+    // waves holding no end, source or probe take the plain step; both paths
+    // cross the two barriers of get_er / get_hl once per step
+    if (!has_role(role) && wp.n == 0) {
+        for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, true, false>(ck, g, get_er, get_hl);
+    } else {
+        run_role<T, C, true, false>(ck, g, role, wp, lane, b, wave_lo, plo, wave_hi, nsteps, slot0, get_er,
+                                    get_hl);
+    }
     if (active) chunk_store<T, C, true, false>(ck, g, s, out, b, off, n, k0, 0, n);
 }
 

@@ -77,6 +77,10 @@ struct ResidentSlot {
 
 // Samples folded into the DFT per twiddle table (table: kTwiddleChunk x F).
 constexpr int kTwiddleChunk = 1024;
+// Tile classes of the temporally blocked executor: 0 vacuum, 1 plasma (both
+// without grid ends, source or probes), 2 tiles touching a CPML layer, 3 the
+// other tiles holding a grid end, the source or a probe.
+constexpr int kTileClasses = 4;
 
 // ---- kernel launchers (kernels1d.hip) ------------------------------------
 template <typename T>
