@@ -116,7 +116,7 @@ def batched_leg(precision="f32", n_slabs=4096, T=8000, reps=2):
     from paper_1709_00821_amd.plasma import FdtdPlasma
     slabs = W.batch_c4(n_slabs=n_slabs, steps=T)
     cells = sum(q.n for q in slabs)
-    tune = TU.pick(precision, cells)
+    tune = TU.pick(precision, cells, batched=True)
     h = FdtdPlasma(slabs, precision=precision, exec="auto", **tune)
     h.run(T)
     h.synchronize()

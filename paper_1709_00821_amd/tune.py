@@ -1,9 +1,12 @@
 """Launch-shape choice for the temporally blocked executor.
 
 pick() returns the (tile_cells, steps_per_pass, tile_waves) to use for a precision and
-grid size: an explicit override, else the best entry measured by
+workload: an explicit override, else the best entry measured by
 `python -m paper_1709_00821_amd.tune` on this GPU (tuning.json next to this
-file), else a default.
+file), else a default.  Two workloads are tuned: one long grid ("large":
+half plasma, CPML ends) and a batch of short independent slabs ("batched":
+Mur ends, a source and two probes per slab, so that tiles holding a grid end
+are a sizeable share).
 """
 from __future__ import annotations
 
@@ -15,16 +18,19 @@ CACHE = os.path.join(HERE, "tuning.json")
 DEFAULT = {"tile_cells": 512, "steps_per_pass": 16, "tile_waves": 1}
 
 
-def _bucket(n: int) -> str:
+def _bucket(n: int, batched: bool = False) -> str:
+    if batched:
+        return "batched"
     return "large" if n >= (1 << 20) else "small"
 
 
-def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0) -> dict:
+def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0,
+         batched: bool = False) -> dict:
     out = dict(DEFAULT)
     if os.path.exists(CACHE):
         try:
             table = json.load(open(CACHE))
-            ent = table.get("gfx950", {}).get(precision, {}).get(_bucket(n))
+            ent = table.get("gfx950", {}).get(precision, {}).get(_bucket(n, batched))
             if ent:
                 out.update({k: int(ent[k]) for k in ("tile_cells", "steps_per_pass", "tile_waves") if k in ent})
         except (OSError, ValueError, KeyError):
@@ -39,13 +45,20 @@ def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0, t
 
 
 def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
-          tiles=(256, 512, 768, 1024), depths=(8, 12, 16, 24, 32, 48, 64), waves=(1,), log=print):
-    """Time run(steps) on a plasma/vacuum grid of n cells for every launch
-    shape; returns [(tile_cells, steps_per_pass, tile_waves, Mcell-updates/s)]."""
+          tiles=(256, 512, 768, 1024), depths=(8, 12, 16, 24, 32, 48, 64), waves=(1,), log=print,
+          workload: str = "large"):
+    """Time run(steps) for every launch shape on a plasma/vacuum grid of n
+    cells (workload "large") or on a batch of n // 4096 slabs of 200-8000
+    cells (workload "batched"); returns [(tile_cells, steps_per_pass,
+    tile_waves, Mcell-updates/s)]."""
     import torch
     from . import workloads as W
     from .plasma import FdtdPlasma
-    p = W.large_c2(n=n, steps=steps)
+    if workload == "batched":
+        p = W.batch_c4(n_slabs=max(1, n // 4096), steps=steps)
+        n = sum(q.n for q in p)
+    else:
+        p = W.large_c2(n=n, steps=steps)
     out = []
     for wv in waves:
         for tc in tiles:
@@ -69,7 +82,7 @@ def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
                 h.close()
                 rate = n * steps / (ms / 1e3) / 1e6
                 out.append((tc, k, wv, rate))
-                log(f"tune {precision} tile_cells={tc:5d} steps_per_pass={k:3d} tile_waves={wv}: "
+                log(f"tune {workload} {precision} tile_cells={tc:5d} steps_per_pass={k:3d} tile_waves={wv}: "
                     f"{ms:8.3f} ms {rate:10.0f} Mcell/s")
     return out
 
@@ -78,6 +91,7 @@ def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="sweep launch shapes and record the best")
     ap.add_argument("--precision", nargs="+", default=["f32", "f64"])
+    ap.add_argument("--workload", nargs="+", default=["large", "batched"], choices=["large", "batched"])
     ap.add_argument("--cells", type=int, default=1 << 22)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--out", default=CACHE)
@@ -92,15 +106,18 @@ def main(argv=None):
         except ValueError:
             table = {}
     g = table.setdefault("gfx950", {})
-    for prec in args.precision:
-        res = sweep(prec, n=args.cells, steps=args.steps, tiles=tuple(args.tiles), depths=tuple(args.depths),
-                    waves=tuple(args.waves), log=lambda m: print(m, flush=True))
-        tc, k, wv, rate = max(res, key=lambda r: r[3])
-        g.setdefault(prec, {})["large"] = {"tile_cells": tc, "steps_per_pass": k, "tile_waves": wv,
-                                          "mcells": round(rate, 1), "cells": args.cells,
-                                          "steps": args.steps}
-        g[prec]["sweep"] = [[a, b, c, round(r, 1)] for a, b, c, r in res]
-        print(f"best {prec}: tile_cells={tc} steps_per_pass={k} tile_waves={wv} {rate:.0f} Mcell/s", flush=True)
+    for wl in args.workload:
+        for prec in args.precision:
+            res = sweep(prec, n=args.cells, steps=args.steps, tiles=tuple(args.tiles), depths=tuple(args.depths),
+                        waves=tuple(args.waves), log=lambda m: print(m, flush=True), workload=wl)
+            tc, k, wv, rate = max(res, key=lambda r: r[3])
+            ent = g.setdefault(prec, {})
+            ent[wl] = {"tile_cells": tc, "steps_per_pass": k, "tile_waves": wv, "mcells": round(rate, 1),
+                       "cells": args.cells, "steps": args.steps,
+                       "sweep": [[a, b, c, round(r, 1)] for a, b, c, r in res]}
+            ent.pop("sweep", None)
+            print(f"best {wl} {prec}: tile_cells={tc} steps_per_pass={k} tile_waves={wv} {rate:.0f} Mcell/s",
+                  flush=True)
     json.dump(table, open(args.out, "w"), indent=1)
 
 
