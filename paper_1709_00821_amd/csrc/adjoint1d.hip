@@ -78,80 +78,6 @@ __global__ void k_adj_source(const double *freqs, int F, double dt, const double
     gsrc[t] = 2.0 * acc;
 }
 
-// ---- recompute of the reverse sweep ---------------------------------------
-
-// E^{n+1} of interior node k from the new H on both sides (k_step_e's
-// step_interior with the H values passed in); writes J^{n+1} if asked.
-template <typename T>
-__device__ __forceinline__ T e_from_h(const Grids &g, const T *E, const double *J, T hk, T hkm, int b,
-                                      int64_t off, int64_t k, int64_t m, double *Jn, bool write)
-{
-    const T curl = hk - hkm;
-    const T Eo = E[k];
-    const double wp2 = g.wp2[off + k];
-    T En;
-    NodeCoef<T> c;
-    if (wp2 != 0.0) {
-        c = node_coef_t<T>(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
-        En = e_update_plasma(Eo, J[k], curl, c);
-    } else {
-        En = e_update_vac<T>(Eo, curl, (T)g.ce);
-    }
-    if (k == g.src[b])
-        En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
-    if (write) *Jn = (wp2 != 0.0) ? j_update<T>(J[k], (double)Eo, (double)En, c) : 0.0;
-    return En;
-}
-
-// One forward step (Mur or PEC ends, no probe samples) in a single launch:
-// state (E, H, J) -> (En, Hn, Jn).  Each thread recomputes the H values its E
-// update reads (its own node's and its left neighbour's; an end node the two
-// beside its neighbour) with the per-node functions and operation order of
-// k_step_h / k_step_e, so the recomputed states equal the forward run's bits.
-template <typename T>
-__global__ void k_recompute1d(Grids g, const T *E, const T *H, const double *J, T *En, T *Hn, double *Jn,
-                              int64_t total, int64_t m)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int b = grid_of_adj(g, i);
-    const int64_t off = g.off[b], n = g.n[b], k = i - off;
-    if (k >= n) return;
-    const T *Eg = E + off, *Hg = H + off;
-    const double *Jg = J + off;
-    const T ch = (T)g.ch;
-    auto hnew = [&](int64_t j) { return h_update<T>(Hg[j], Eg[j], Eg[j + 1], ch); };
-    if (k <= n - 2) Hn[off + k] = hnew(k);
-    T e;
-    double jn = 0.0;
-    if (k == 0 || k == n - 1) {
-        if (g.bc == 0) {  // first-order Mur: E0' = E1 + cm (E1' - E0)
-            const int64_t kn = (k == 0) ? 1 : n - 2;
-            const T Enb = e_from_h<T>(g, Eg, Jg, hnew(kn), hnew(kn - 1), b, off, kn, m, nullptr, false);
-            e = Eg[kn] + (T)g.cm * (Enb - Eg[k]);
-        } else {
-            e = (T)0;
-        }
-    } else {
-        e = e_from_h<T>(g, Eg, Jg, hnew(k), hnew(k - 1), b, off, k, m, &jn, true);
-    }
-    En[off + k] = e;
-    Jn[off + k] = jn;
-}
-
-template <typename T>
-void launch_recompute1d(const Grids &g, const T *E, const T *H, const double *J, T *En, T *Hn, double *Jn,
-                        int64_t total, int64_t m, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_recompute1d<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g, E, H, J, En,
-                       Hn, Jn, total, m);
-}
-
-template void launch_recompute1d<float>(const Grids &, const float *, const float *, const double *, float *,
-                                        float *, double *, int64_t, int64_t, hipStream_t);
-template void launch_recompute1d<double>(const Grids &, const double *, const double *, const double *,
-                                         double *, double *, double *, int64_t, int64_t, hipStream_t);
-
 template <typename T>
 struct AdjView {
     const T *lE, *lH, *lJ;      // lambda^{m+1}

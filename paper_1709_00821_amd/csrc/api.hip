@@ -92,6 +92,9 @@ struct fdtd_plasma {
     // tiled executor
     std::vector<Tile> tiles_host;
     Tile *d_tiles = nullptr;
+    Tile *d_adj_tiles = nullptr;   // recompute tiles of the adjoint (one list)
+    int64_t n_adj_tiles = 0;
+    double *d_adj_srcv = nullptr;  // source values of the segment being recomputed
     int64_t ntiles[kTileClasses] = {0, 0, 0, 0};
     int64_t tile_first[kTileClasses] = {0, 0, 0, 0};
     int tileC = 8, Kh = 16, tileW = 1;
@@ -273,7 +276,8 @@ struct Plan {
     int64_t o_off = 0, o_n = 0, o_src = 0, o_probe = 0, o_wp2 = 0, o_nu = 0, o_freqs = 0, o_samp = 0, o_srcv = 0,
             o_X = 0, o_Xtmp = 0, o_tw = 0, o_cpml = 0;
     int64_t o_E[2] = {0, 0}, o_H[2] = {0, 0}, o_J[2] = {0, 0}, o_psiE[2] = {0, 0}, o_psiH[2] = {0, 0};
-    int64_t o_tiles = 0, o_slots = 0;
+    int64_t o_tiles = 0, o_slots = 0, o_adj_tiles = 0, o_adj_srcv = 0;
+    std::vector<Tile> adj_tiles;
     int64_t o_ck = 0, o_seg = 0, o_lam[2][3] = {{0, 0, 0}, {0, 0, 0}}, o_grad = 0, o_tab = 0,
             o_gsrc = 0, o_loss = 0, o_xref = 0, o_G = 0;
     int64_t ck_T = 0, ck_s = 0, ck_n = 0;
@@ -497,6 +501,16 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         p.o_grad = L.take(8 * p.nodes);
         p.o_tab = L.take(8 * 11 * p.nodes);
         p.o_gsrc = L.take(8 * d->batch * p.ck_T);
+        // the reverse sweep recomputes each segment with register tiles of
+        // kTraceCells nodes, kTraceHalo steps per launch
+        Plan q;
+        q.tileC = kTraceCells / 64;
+        q.tileW = 1;
+        q.Kh = kTraceHalo;
+        build_tiles(d, q);
+        p.adj_tiles = q.tiles;
+        p.o_adj_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.adj_tiles.size()));
+        p.o_adj_srcv = L.take(8 * p.ck_s);
     }
     p.o_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.tiles.size()));
     p.o_slots = L.take((int64_t)sizeof(ResidentSlot) * std::max<size_t>(1, p.slots.size()));
@@ -803,6 +817,11 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         h->d_gsrc = (double *)(w + p.o_gsrc);
     }
     h->d_tiles = (Tile *)(w + p.o_tiles);
+    if (p.o_adj_tiles) {
+        h->d_adj_tiles = (Tile *)(w + p.o_adj_tiles);
+        h->n_adj_tiles = (int64_t)p.adj_tiles.size();
+        h->d_adj_srcv = (double *)(w + p.o_adj_srcv);
+    }
     h->d_slots = (ResidentSlot *)(w + p.o_slots);
 
     // padded material arrays (zero in the padding)
@@ -831,6 +850,8 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         e = H2D(h->d_tiles, p.tiles.data(), sizeof(Tile) * p.tiles.size());
     if (e == hipSuccess && !p.slots.empty())
         e = H2D(h->d_slots, p.slots.data(), sizeof(ResidentSlot) * p.slots.size());
+    if (e == hipSuccess && !p.adj_tiles.empty())
+        e = H2D(h->d_adj_tiles, p.adj_tiles.data(), sizeof(Tile) * p.adj_tiles.size());
     if (e != hipSuccess)
         return undo(fail(FDTD_E_DEVICE, "host-to-device copy failed: %s", hipGetErrorString(e)));
     if (desc->bc == FDTD_BC_CPML) {
@@ -1015,8 +1036,10 @@ template <typename T>
 int reverse_sweep(fdtd_plasma *h, int64_t Tn, int probe)
 {
     Grids g = h->grids();
-    Grids gq = g;
-    gq.P = 0;                          // recompute: no probe samples
+    Grids gt = g;                      // recompute: no probe samples, the segment's source table
+    gt.P = 0;
+    gt.srcv = h->d_adj_srcv;
+    gt.SB = (int)h->ck_s;
     const int64_t sb = round_up(8 * h->nodes, kAlign), ck3 = 3 * sb;
     auto segE = [&](int64_t i) { return (T *)(h->d_seg + i * ck3); };
     auto segH = [&](int64_t i) { return (T *)(h->d_seg + i * ck3 + sb); };
@@ -1029,9 +1052,12 @@ int reverse_sweep(fdtd_plasma *h, int64_t Tn, int probe)
     for (int64_t j = nseg - 1; j >= 0; --j) {
         const int64_t m0 = j * h->ck_s, m1 = std::min<int64_t>(Tn, m0 + h->ck_s);
         launch_copy(h->d_seg, h->d_ck + j * ck3, ck3, h->stream);
-        for (int64_t i = 0; i < m1 - m0; ++i)
-            launch_recompute1d<T>(gq, segE(i), segH(i), segJ(i), segE(i + 1), segH(i + 1), segJ(i + 1), h->nodes,
-                                  m0 + i + 1, h->stream);
+        // forward states of steps m0 .. m1 into the segment slots 0 .. m1 - m0,
+        // kTraceHalo steps per launch
+        launch_src_table(g, m0 + 1, (int)(m1 - m0), h->d_adj_srcv, h->stream);
+        for (int64_t i = 0; i < m1 - m0; i += kTraceHalo)
+            launch_trace<T>(gt, h->d_seg, ck3, sb, h->d_adj_tiles, h->n_adj_tiles,
+                            (int)std::min<int64_t>(kTraceHalo, m1 - m0 - i), (int)i, h->stream);
         for (int64_t m = m1 - 1; m >= m0; --m) {
             const int64_t i = m - m0;
             const T *lam[3] = {(const T *)h->d_lam[lc][0], (const T *)h->d_lam[lc][1],

@@ -494,10 +494,10 @@ __device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_
 // run the wave issues nothing but the probe stores, which it never waits on.
 // (Every cross-lane read here takes a value all lanes computed: a value
 // computed only in some lanes would be stale in the lane that is read.)
-template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
+template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl, typename Post>
 __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g, const WaveRole &r,
                                          const WaveProbes &wp, int lane, int b, int64_t wave_lo, int64_t plo,
-                                         int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl)
+                                         int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
 {
     EndCarry<T> c;
     ends_init<T, C>(ck.E, r, c);
@@ -512,6 +512,7 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Gr
         auto one = [&](int st) {
             const double sv = (r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
             chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
+            post(base + st);
             if (wp.n > 2) {
                 wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
             } else {
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
         wp.n = 0;
         if (tl.flags & TILE_PROBE) wp = wave_probes_find<C>(g, b, tl.lo, tl.out_lo, tl.out_hi);
         run_role<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0, er,
-                                     hl);
+                                     hl, [](int) {});
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
@@ -632,7 +633,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
     if (!has_role(role) && wp.n == 0) {
         for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, PLASMA, CPML>(ck, g, er, hl);
     } else {
-        run_role<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, wave_lo, plo, phi, nsteps, slot0, er, hl);
+        run_role<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, wave_lo, plo, phi, nsteps, slot0, er, hl,
+                                     [](int) {});
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
@@ -703,6 +705,71 @@ template void launch_tiled<float>(const Grids &, State<float> &, int, const Tile
 template void launch_tiled<double>(const Grids &, State<double> &, int, const Tile *, int64_t, int,
                                    int, int, int, hipStream_t, int);
 
+// ------------------------------------------------------------ trace
+
+// Forward recompute for the adjoint: the tiles of every grid advance nsteps
+// steps from segment slot slot0 and store the state of their output nodes
+// after every step into slots slot0 + 1 .. slot0 + nsteps (slot i at
+// seg + i * slot_bytes: E [nodes], H at + arr_bytes, J (FP64) at + 2 arr_bytes).
+// Same per-node functions as k_tiled, hence the forward run's bits.  Tiles
+// read only slot slot0, which no tile of the launch writes.  Mur or PEC ends;
+// no probes (g.P = 0); the source values come from g.srcv indexed by slot.
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_trace(Grids g, char *seg, int64_t slot_bytes, int64_t arr_bytes,
+                                               const Tile *tiles, int64_t ntiles, int nsteps, int slot0)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t t = blk * (blockDim.x >> 6) + uniform(threadIdx.x >> 6);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const int b = tl.grid;
+    const int64_t off = g.off[b], n = g.n[b];
+    const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
+    auto slotE = [&](int i) { return (T *)(seg + (int64_t)i * slot_bytes); };
+    auto slotH = [&](int i) { return (T *)(seg + (int64_t)i * slot_bytes + arr_bytes); };
+    auto slotJ = [&](int i) { return (double *)(seg + (int64_t)i * slot_bytes + 2 * arr_bytes); };
+    State<T> s0;
+    s0.E[0] = slotE(slot0);
+    s0.H[0] = slotH(slot0);
+    s0.J[0] = slotJ(slot0);
+    Chunk<T, C, true, false> ck;
+    chunk_load<T, C, true, false>(ck, g, s0, 0, b, off, n, k0, tl.hi);
+    auto er = [](T e0) { return shfl_down1(e0); };
+    auto hl = [](T h) { return shfl_up1(h); };
+    auto post = [&](int st) {
+        const int i = slot0 + st + 1;
+        store_chunk<T, C>(slotE(i) + off, k0, tl.out_lo, tl.out_hi, ck.E);
+        store_chunk<T, C>(slotH(i) + off, k0, tl.out_lo, tl.out_hi < n ? tl.out_hi : n - 1, ck.H);
+        store_chunk<double, C>(slotJ(i) + off, k0, tl.out_lo, tl.out_hi, ck.J);
+    };
+    const WaveRole role = wave_role<C>(g, b, n, tl.lo, tl.hi);
+    if (!has_role(role)) {
+        for (int st = 0; st < nsteps; ++st) {
+            chunk_step_plain<T, C, true, false>(ck, g, er, hl);
+            post(st);
+        }
+    } else {
+        WaveProbes wp;
+        wp.n = 0;
+        run_role<T, C, true, false>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0, er, hl,
+                                    post);
+    }
+}
+
+template <typename T>
+void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_bytes, const Tile *tiles,
+                  int64_t ntiles, int nsteps, int slot0, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_trace<T, 8>), dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, g, seg, slot_bytes,
+                       arr_bytes, tiles, ntiles, nsteps, slot0);
+}
+
+template void launch_trace<float>(const Grids &, char *, int64_t, int64_t, const Tile *, int64_t, int, int,
+                                  hipStream_t);
+template void launch_trace<double>(const Grids &, char *, int64_t, int64_t, const Tile *, int64_t, int, int,
+                                   hipStream_t);
+
 // ------------------------------------------------------------- resident
 
 // One workgroup per bin of grids; slots[bin*WAVES + w] says which grid wave w
@@ -764,7 +831,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
         for (int st = 0; st < nsteps; ++st) chunk_step_plain<T, C, true, false>(ck, g, get_er, get_hl);
     } else {
         run_role<T, C, true, false>(ck, g, role, wp, lane, b, wave_lo, plo, wave_hi, nsteps, slot0, get_er,
-                                    get_hl);
+                                    get_hl, [](int) {});
     }
     if (active) chunk_store<T, C, true, false>(ck, g, s, out, b, off, n, k0, 0, n);
 }

@@ -93,6 +93,14 @@ template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
                   int klass, int C, int nsteps, int slot0, hipStream_t st, int waves = 1);
 
+// Forward recompute of nsteps steps from segment slot slot0, every step's
+// state stored (tiles of kTraceCells nodes with a kTraceHalo halo, nsteps <=
+// kTraceHalo).
+template <typename T>
+void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_bytes, const Tile *tiles,
+                  int64_t ntiles, int nsteps, int slot0, hipStream_t st);
+constexpr int kTraceCells = 512, kTraceHalo = 48;
+
 // Reads buffer cur, writes buffer out (cur itself for a whole-run resident
 // call, the other buffer when bins and tiles share a pass).
 template <typename T>
@@ -122,10 +130,5 @@ void launch_adj_step(const Grids &g, const T *const lam[3], T *const out[3], con
                      const double *gsrc, int64_t T_, int64_t m, int probe, double *grad,
                      hipStream_t st);
 void launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
-// One forward step (Mur/PEC ends, no probes) as a single launch, for the
-// reverse sweep's recompute; same bits as launch_step.
-template <typename T>
-void launch_recompute1d(const Grids &g, const T *E, const T *H, const double *J, T *En, T *Hn, double *Jn,
-                        int64_t total, int64_t m, hipStream_t st);
 
 }  // namespace fdtdp
