@@ -105,7 +105,8 @@ __global__ void k_adj_step(Grids g, AdjView<T> v, const double *tab, int64_t tot
     const double src = gsrc[(int64_t)b * T_ + m];      // dL/dE^{m+1}[pc]
     // lambda_E^{m+1} after the probe's adjoint source, at grid node j
     auto lEp = [&](int64_t j) -> double {
-        return (double)v.lE[off + j] + (j == pc ? src : 0.0);
+        const double l = (double)v.lE[off + j];
+        return j == pc ? l + src : l;
     };
     // adjoint of E* at interior node j (1..n-2): ends (Mur) and the J update's b2
     auto lEs = [&](int64_t j) -> double {

@@ -94,6 +94,8 @@ struct fdtd_plasma {
     Tile *d_tiles = nullptr;
     Tile *d_adj_tiles = nullptr;   // recompute tiles of the adjoint (one list)
     int64_t n_adj_tiles = 0;
+    Tile *d_rev_tiles = nullptr;   // reverse-step tiles of the adjoint (one list)
+    int64_t n_rev_tiles = 0;
     double *d_adj_srcv = nullptr;  // source values of the segment being recomputed
     int64_t ntiles[kTileClasses] = {0, 0, 0, 0};
     int64_t tile_first[kTileClasses] = {0, 0, 0, 0};
@@ -276,8 +278,8 @@ struct Plan {
     int64_t o_off = 0, o_n = 0, o_src = 0, o_probe = 0, o_wp2 = 0, o_nu = 0, o_freqs = 0, o_samp = 0, o_srcv = 0,
             o_X = 0, o_Xtmp = 0, o_tw = 0, o_cpml = 0;
     int64_t o_E[2] = {0, 0}, o_H[2] = {0, 0}, o_J[2] = {0, 0}, o_psiE[2] = {0, 0}, o_psiH[2] = {0, 0};
-    int64_t o_tiles = 0, o_slots = 0, o_adj_tiles = 0, o_adj_srcv = 0;
-    std::vector<Tile> adj_tiles;
+    int64_t o_tiles = 0, o_slots = 0, o_adj_tiles = 0, o_adj_srcv = 0, o_rev_tiles = 0;
+    std::vector<Tile> adj_tiles, rev_tiles;
     int64_t o_ck = 0, o_seg = 0, o_lam[2][3] = {{0, 0, 0}, {0, 0, 0}}, o_grad = 0, o_tab = 0,
             o_gsrc = 0, o_loss = 0, o_xref = 0, o_G = 0;
     int64_t ck_T = 0, ck_s = 0, ck_n = 0;
@@ -509,7 +511,16 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         q.Kh = kTraceHalo;
         build_tiles(d, q);
         p.adj_tiles = q.tiles;
+        // and runs the transposed steps on tiles of kAdjCells nodes, up to
+        // kAdjHalo steps per launch
+        Plan r;
+        r.tileC = kAdjCells / 64;
+        r.tileW = 1;
+        r.Kh = kAdjHalo;
+        build_tiles(d, r);
+        p.rev_tiles = r.tiles;
         p.o_adj_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.adj_tiles.size()));
+        p.o_rev_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.rev_tiles.size()));
         p.o_adj_srcv = L.take(8 * p.ck_s);
     }
     p.o_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.tiles.size()));
@@ -821,6 +832,8 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         h->d_adj_tiles = (Tile *)(w + p.o_adj_tiles);
         h->n_adj_tiles = (int64_t)p.adj_tiles.size();
         h->d_adj_srcv = (double *)(w + p.o_adj_srcv);
+        h->d_rev_tiles = (Tile *)(w + p.o_rev_tiles);
+        h->n_rev_tiles = (int64_t)p.rev_tiles.size();
     }
     h->d_slots = (ResidentSlot *)(w + p.o_slots);
 
@@ -852,6 +865,8 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         e = H2D(h->d_slots, p.slots.data(), sizeof(ResidentSlot) * p.slots.size());
     if (e == hipSuccess && !p.adj_tiles.empty())
         e = H2D(h->d_adj_tiles, p.adj_tiles.data(), sizeof(Tile) * p.adj_tiles.size());
+    if (e == hipSuccess && !p.rev_tiles.empty())
+        e = H2D(h->d_rev_tiles, p.rev_tiles.data(), sizeof(Tile) * p.rev_tiles.size());
     if (e != hipSuccess)
         return undo(fail(FDTD_E_DEVICE, "host-to-device copy failed: %s", hipGetErrorString(e)));
     if (desc->bc == FDTD_BC_CPML) {
@@ -1058,14 +1073,41 @@ int reverse_sweep(fdtd_plasma *h, int64_t Tn, int probe)
         for (int64_t i = 0; i < m1 - m0; i += kTraceHalo)
             launch_trace<T>(gt, h->d_seg, ck3, sb, h->d_adj_tiles, h->n_adj_tiles,
                             (int)std::min<int64_t>(kTraceHalo, m1 - m0 - i), (int)i, h->stream);
-        for (int64_t m = m1 - 1; m >= m0; --m) {
-            const int64_t i = m - m0;
-            const T *lam[3] = {(const T *)h->d_lam[lc][0], (const T *)h->d_lam[lc][1],
-                               (const T *)h->d_lam[lc][2]};
-            T *out[3] = {(T *)h->d_lam[lc ^ 1][0], (T *)h->d_lam[lc ^ 1][1], (T *)h->d_lam[lc ^ 1][2]};
-            launch_adj_step<T>(g, lam, out, segE(i), segJ(i), segH(i + 1), segE(i + 1), h->d_tab,
-                               h->nodes, h->d_gsrc, Tn, m, probe, h->d_grad, h->stream);
-            lc ^= 1;
+        if (h->exec == FDTD_EXEC_STEP) {
+            // the per-step reference: one launch per transposed step
+            for (int64_t m = m1 - 1; m >= m0; --m) {
+                const int64_t i = m - m0;
+                const T *lam[3] = {(const T *)h->d_lam[lc][0], (const T *)h->d_lam[lc][1],
+                                   (const T *)h->d_lam[lc][2]};
+                T *out[3] = {(T *)h->d_lam[lc ^ 1][0], (T *)h->d_lam[lc ^ 1][1], (T *)h->d_lam[lc ^ 1][2]};
+                launch_adj_step<T>(g, lam, out, segE(i), segJ(i), segH(i + 1), segE(i + 1), h->d_tab,
+                                   h->nodes, h->d_gsrc, Tn, m, probe, h->d_grad, h->stream);
+                lc ^= 1;
+            }
+        } else {
+            // register tiles: up to kAdjHalo transposed steps per launch, same bits
+            for (int64_t mt = m1 - 1; mt >= m0; mt -= kAdjHalo) {
+                const int k = (int)std::min<int64_t>(kAdjHalo, mt - m0 + 1);
+                AdjTileArgs<T> a;
+                a.lE = (const T *)h->d_lam[lc][0];
+                a.lH = (const T *)h->d_lam[lc][1];
+                a.lJ = (const T *)h->d_lam[lc][2];
+                a.nE = (T *)h->d_lam[lc ^ 1][0];
+                a.nH = (T *)h->d_lam[lc ^ 1][1];
+                a.nJ = (T *)h->d_lam[lc ^ 1][2];
+                a.tab = h->d_tab;
+                a.total = h->nodes;
+                a.seg = h->d_seg;
+                a.slot_bytes = ck3;
+                a.arr_bytes = sb;
+                a.m0 = m0;
+                a.gsrc = h->d_gsrc;
+                a.T_ = Tn;
+                a.probe = probe;
+                a.grad = h->d_grad;
+                launch_adj_tiled<T>(g, a, h->d_rev_tiles, h->n_rev_tiles, mt, k, h->stream);
+                lc ^= 1;
+            }
         }
     }
     hipError_t e = hipGetLastError();

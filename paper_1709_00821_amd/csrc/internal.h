@@ -101,6 +101,26 @@ void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_byt
                   int64_t ntiles, int nsteps, int slot0, hipStream_t st);
 constexpr int kTraceCells = 512, kTraceHalo = 48;
 
+// Reverse sweep on register tiles (kAdjCells nodes, kAdjHalo halo): nsteps
+// transposed steps m = mtop, mtop - 1, .. per launch.
+template <typename T>
+struct AdjTileArgs {
+    const T *lE, *lH, *lJ;      // lambda^{mtop+1} (read)
+    T *nE, *nH, *nJ;            // lambda^{mtop+1-nsteps} (written, output nodes)
+    const double *tab;          // [11][total] coefficients and wp2-derivatives
+    int64_t total;
+    const char *seg;            // forward states: slot i = m - m0 (E, H at + arr_bytes, J at + 2 arr_bytes)
+    int64_t slot_bytes, arr_bytes, m0;
+    const double *gsrc;         // [batch][T_] dL/dE at the probe
+    int64_t T_;
+    int probe;
+    double *grad;               // [total]
+};
+template <typename T>
+void launch_adj_tiled(const Grids &g, const AdjTileArgs<T> &a, const Tile *tiles, int64_t ntiles, int64_t mtop,
+                      int nsteps, hipStream_t st);
+constexpr int kAdjCells = 256, kAdjHalo = 48;
+
 // Reads buffer cur, writes buffer out (cur itself for a whole-run resident
 // call, the other buffer when bins and tiles share a pass).
 template <typename T>
