@@ -95,10 +95,12 @@ typedef struct {
     const int64_t *probe_cells;  /* host [batch][n_probes]: nodes in 0..n-1 */
     const double *freqs_hz;      /* host [n_freqs] */
     int32_t cpml_cells;          /* CPML thickness in nodes (bc = CPML) */
-    int32_t tile_cells;          /* TILED: nodes per register tile (64*C); 0 = default */
+    int32_t tile_cells;          /* TILED: nodes per register tile (64*C: 256, 512, 768 or 1024);
+                                    0 = 512 */
     double cpml_m;               /* CPML grading order; <= 0 means 3 */
     double cpml_sigma_max;       /* <= 0 means 0.8 (m+1)/(eta0 dz) */
-    int32_t steps_per_pass;      /* TILED: time steps per launch (halo depth); 0 = default */
+    int32_t steps_per_pass;      /* TILED: time steps per launch (halo depth), a multiple of 4 in
+                                    [4, 64]; 0 = 48 */
     int32_t checkpoint_steps;    /* with FDTD_FLAG_CHECKPOINT: longest run the checkpoint and
                                     adjoint storage is sized for (>= 1) */
     int32_t tile_waves;          /* TILED: waves per tile (1, 2, 4 or 8; neighbouring waves of a

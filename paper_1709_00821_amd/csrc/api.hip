@@ -418,9 +418,9 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     p.psi_bytes = d->bc == FDTD_BC_CPML ? d->batch * 2 * d->cpml_cells * es : 16;
 
     // executor choice
-    p.tileC = d->tile_cells ? d->tile_cells / 64 : (es == 8 ? 8 : 8);
+    p.tileC = d->tile_cells ? d->tile_cells / 64 : 8;
     p.tileW = d->tile_waves ? d->tile_waves : 1;
-    p.Kh = d->steps_per_pass ? d->steps_per_pass : 16;
+    p.Kh = d->steps_per_pass ? d->steps_per_pass : 48;
     p.resC = 8;
     p.resWaves = 8;   // 512-thread workgroups keep the FP64 coefficients in registers without spills
     p.exec = d->exec;

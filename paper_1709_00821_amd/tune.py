@@ -15,7 +15,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_cells": 512, "steps_per_pass": 16, "tile_waves": 1}
+DEFAULT = {"tile_cells": 512, "steps_per_pass": 48, "tile_waves": 1}
 
 
 def _bucket(n: int, batched: bool = False) -> str:
