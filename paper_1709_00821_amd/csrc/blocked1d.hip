@@ -761,8 +761,8 @@ template <typename T>
 void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_bytes, const Tile *tiles,
                   int64_t ntiles, int nsteps, int slot0, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_trace<T, 8>), dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, g, seg, slot_bytes,
-                       arr_bytes, tiles, ntiles, nsteps, slot0);
+    hipLaunchKernelGGL((k_trace<T, kTraceCells / 64>), dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, g, seg,
+                       slot_bytes, arr_bytes, tiles, ntiles, nsteps, slot0);
 }
 
 template void launch_trace<float>(const Grids &, char *, int64_t, int64_t, const Tile *, int64_t, int, int,
@@ -822,15 +822,32 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
     const int p_lane = uniform(has_p ? (pc - tl.lo) / C : -1), p_reg = uniform(has_p ? (pc - tl.lo) % C : 0);
     const int nn = (int)n;
     auto slotp = [&](int64_t m, int q) { return a.seg + (m - a.m0) * a.slot_bytes + q * a.arr_bytes; };
+    // forward states E^m, J^m, H^{m+1/2}, E^{m+1} of the next step are loaded
+    // one step ahead (E^{m+1} of step m-1 is this step's E^m)
+    T ne0[C], nhh[C], ne1[C];
+    double nj0[C];
+    load_chunk<T, C>((const T *)slotp(mtop, 0) + off, k0, tl.hi, ne0);
+    load_chunk<double, C>((const double *)slotp(mtop, 2) + off, k0, tl.hi, nj0);
+    load_chunk<T, C>((const T *)slotp(mtop + 1, 1) + off, k0, tl.hi, nhh);
+    load_chunk<T, C>((const T *)slotp(mtop + 1, 0) + off, k0, tl.hi, ne1);
     for (int st = 0; st < nsteps; ++st) {
         const int64_t m = mtop - st;
-        // forward states E^m, J^m, H^{m+1/2}, E^{m+1}
         T e0[C], hh[C], e1[C];
         double j0[C];
-        load_chunk<T, C>((const T *)slotp(m, 0) + off, k0, tl.hi, e0);
-        load_chunk<double, C>((const double *)slotp(m, 2) + off, k0, tl.hi, j0);
-        load_chunk<T, C>((const T *)slotp(m + 1, 1) + off, k0, tl.hi, hh);
-        load_chunk<T, C>((const T *)slotp(m + 1, 0) + off, k0, tl.hi, e1);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            e0[i] = ne0[i];
+            j0[i] = nj0[i];
+            hh[i] = nhh[i];
+            e1[i] = ne1[i];
+        }
+        if (st + 1 < nsteps) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) ne1[i] = e0[i];
+            load_chunk<T, C>((const T *)slotp(m - 1, 0) + off, k0, tl.hi, ne0);
+            load_chunk<double, C>((const double *)slotp(m - 1, 2) + off, k0, tl.hi, nj0);
+            load_chunk<T, C>((const T *)slotp(m, 1) + off, k0, tl.hi, nhh);
+        }
         const double src = has_p ? a.gsrc[(int64_t)b * a.T_ + m] : 0.0;
         double lEp[C], es[C], lHn[C];
 #pragma unroll

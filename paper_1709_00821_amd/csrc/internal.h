@@ -99,7 +99,7 @@ void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64
 template <typename T>
 void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_bytes, const Tile *tiles,
                   int64_t ntiles, int nsteps, int slot0, hipStream_t st);
-constexpr int kTraceCells = 512, kTraceHalo = 48;
+constexpr int kTraceCells = 256, kTraceHalo = 48;
 
 // Reverse sweep on register tiles (kAdjCells nodes, kAdjHalo halo): nsteps
 // transposed steps m = mtop, mtop - 1, .. per launch.
