@@ -140,13 +140,15 @@ def adjoint_leg(precision="f32"):
     forward with sqrt(T) checkpoints + reverse sweep with recompute."""
     import torch
     from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd import tune as TU
     from paper_1709_00821_amd.plasma import FdtdPlasma
     p = W.adjoint_c5()
     T = p.steps
+    tune = TU.pick(precision, p.n)
     with FdtdPlasma(p.vacuum(), precision="f64", exec="tiled") as hv:
         hv.run(T)
         xv = hv.spectra()[0, 0].reshape(1, -1)
-    h = FdtdPlasma(p, precision=precision, exec="tiled", checkpoint=T)
+    h = FdtdPlasma(p, precision=precision, exec="tiled", checkpoint=T, **tune)
     h.run(T)
     h.grad_r2(T, xv)                 # first call captures the reverse sweep's graph
     h.synchronize()
@@ -164,7 +166,8 @@ def adjoint_leg(precision="f32"):
     return {"value": round(p.n * T / (tot / 1e3) / 1e6, 1), "unit": "forward-equivalent Mcell/s",
             "forward_ms": round(fwd_ms, 3), "reverse_ms": round(adj_ms, 3),
             "nodes": p.n, "time_steps": T, "precision": precision,
-            "checkpoint_interval": int(math.ceil(math.sqrt(T)))}
+            "checkpoint_interval": int(math.ceil(math.sqrt(T))), "forward_tile_cells": tune["tile_cells"],
+            "forward_steps_per_pass": tune["steps_per_pass"]}
 
 
 def c1_leg(reps=5):

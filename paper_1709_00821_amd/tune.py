@@ -3,10 +3,11 @@
 pick() returns the (tile_cells, steps_per_pass, tile_waves) to use for a precision and
 workload: an explicit override, else the best entry measured by
 `python -m paper_1709_00821_amd.tune` on this GPU (tuning.json next to this
-file), else a default.  Two workloads are tuned: one long grid ("large":
-half plasma, CPML ends) and a batch of short independent slabs ("batched":
-Mur ends, a source and two probes per slab, so that tiles holding a grid end
-are a sizeable share).
+file), else a default.  Three workloads are tuned: one long grid ("large":
+half plasma, CPML ends), a batch of short independent slabs ("batched": Mur
+ends, a source and two probes per slab, so that tiles holding a grid end are
+a sizeable share) and one short grid ("small": 8000 nodes, where a launch is
+a few waves and latency rather than throughput decides).
 """
 from __future__ import annotations
 
@@ -48,15 +49,19 @@ def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
           tiles=(256, 512, 768, 1024), depths=(8, 12, 16, 24, 32, 48, 64), waves=(1,), log=print,
           workload: str = "large"):
     """Time run(steps) for every launch shape on a plasma/vacuum grid of n
-    cells (workload "large") or on a batch of n // 4096 slabs of 200-8000
-    cells (workload "batched"); returns [(tile_cells, steps_per_pass,
-    tile_waves, Mcell-updates/s)]."""
+    cells (workload "large"), on a batch of n // 4096 slabs of 200-8000
+    cells (workload "batched") or on one 8000-node grid (workload "small");
+    returns ([(tile_cells, steps_per_pass, tile_waves, Mcell-updates/s)],
+    nodes of the workload)."""
     import torch
     from . import workloads as W
     from .plasma import FdtdPlasma
     if workload == "batched":
         p = W.batch_c4(n_slabs=max(1, n // 4096), steps=steps)
         n = sum(q.n for q in p)
+    elif workload == "small":
+        p = W.adjoint_c5(steps=steps)
+        n = p.n
     else:
         p = W.large_c2(n=n, steps=steps)
     out = []
@@ -84,14 +89,15 @@ def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
                 out.append((tc, k, wv, rate))
                 log(f"tune {workload} {precision} tile_cells={tc:5d} steps_per_pass={k:3d} tile_waves={wv}: "
                     f"{ms:8.3f} ms {rate:10.0f} Mcell/s")
-    return out
+    return out, n
 
 
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="sweep launch shapes and record the best")
     ap.add_argument("--precision", nargs="+", default=["f32", "f64"])
-    ap.add_argument("--workload", nargs="+", default=["large", "batched"], choices=["large", "batched"])
+    ap.add_argument("--workload", nargs="+", default=["large", "batched", "small"],
+                    choices=["large", "batched", "small"])
     ap.add_argument("--cells", type=int, default=1 << 22)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--out", default=CACHE)
@@ -108,12 +114,13 @@ def main(argv=None):
     g = table.setdefault("gfx950", {})
     for wl in args.workload:
         for prec in args.precision:
-            res = sweep(prec, n=args.cells, steps=args.steps, tiles=tuple(args.tiles), depths=tuple(args.depths),
-                        waves=tuple(args.waves), log=lambda m: print(m, flush=True), workload=wl)
+            res, cells = sweep(prec, n=args.cells, steps=args.steps, tiles=tuple(args.tiles),
+                               depths=tuple(args.depths), waves=tuple(args.waves),
+                               log=lambda m: print(m, flush=True), workload=wl)
             tc, k, wv, rate = max(res, key=lambda r: r[3])
             ent = g.setdefault(prec, {})
             ent[wl] = {"tile_cells": tc, "steps_per_pass": k, "tile_waves": wv, "mcells": round(rate, 1),
-                       "cells": args.cells, "steps": args.steps,
+                       "cells": cells, "steps": args.steps,
                        "sweep": [[a, b, c, round(r, 1)] for a, b, c, r in res]}
             ent.pop("sweep", None)
             print(f"best {wl} {prec}: tile_cells={tc} steps_per_pass={k} tile_waves={wv} {rate:.0f} Mcell/s",
