@@ -254,7 +254,7 @@ def c3_leg(precision="f32", n=384, T=2000, prof_steps=64):
 
 # the sources the 1D tiled kernels are compiled from (what the counter
 # summary describes); other files of the library do not change them
-TILED_SOURCES = ("physics.h", "internal.h", "blocked1d.hip")
+TILED_SOURCES = ("physics.h", "internal.h", "tile1d.h", "blocked1d.hip")
 
 
 def kernel_source_hash() -> str:

@@ -8,7 +8,7 @@
 //   lambda_E* (dCA E^n - dCJ J^n - dCH curl H^{n+1/2}) + lambda_J (db1 E^n + db2 E^{n+1}).
 #include <hip/hip_runtime.h>
 
-#include "internal.h"
+#include "tile1d.h"
 
 namespace fdtdp {
 
@@ -208,5 +208,267 @@ void launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
     hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src,
                        n16);
 }
+
+// ------------------------------------------------------------ trace
+
+// Forward recompute for the adjoint: the tiles of every grid advance nsteps
+// steps from segment slot slot0 and store the state of their output nodes
+// after every step into slots slot0 + 1 .. slot0 + nsteps (slot i at
+// seg + i * slot_bytes: E [nodes], H at + arr_bytes, J (FP64) at + 2 arr_bytes).
+// Same per-node functions as k_tiled, hence the forward run's bits.  Tiles
+// read only slot slot0, which no tile of the launch writes.  Mur or PEC ends;
+// no probes (g.P = 0); the source values come from g.srcv indexed by slot.
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_trace(Grids g, char *seg, int64_t slot_bytes, int64_t arr_bytes,
+                                               const Tile *tiles, int64_t ntiles, int nsteps, int slot0)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t t = blk * (blockDim.x >> 6) + uniform(threadIdx.x >> 6);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const int b = tl.grid;
+    const int64_t off = g.off[b], n = g.n[b];
+    const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
+    auto slotE = [&](int i) { return (T *)(seg + (int64_t)i * slot_bytes); };
+    auto slotH = [&](int i) { return (T *)(seg + (int64_t)i * slot_bytes + arr_bytes); };
+    auto slotJ = [&](int i) { return (double *)(seg + (int64_t)i * slot_bytes + 2 * arr_bytes); };
+    State<T> s0;
+    s0.E[0] = slotE(slot0);
+    s0.H[0] = slotH(slot0);
+    s0.J[0] = slotJ(slot0);
+    Chunk<T, C, true, false> ck;
+    chunk_load<T, C, true, false>(ck, g, s0, 0, b, off, n, k0, tl.hi);
+    auto er = [](T e0) { return shfl_down1(e0); };
+    auto hl = [](T h) { return shfl_up1(h); };
+    auto post = [&](int st) {
+        const int i = slot0 + st + 1;
+        store_chunk<T, C>(slotE(i) + off, k0, tl.out_lo, tl.out_hi, ck.E);
+        store_chunk<T, C>(slotH(i) + off, k0, tl.out_lo, tl.out_hi < n ? tl.out_hi : n - 1, ck.H);
+        store_chunk<double, C>(slotJ(i) + off, k0, tl.out_lo, tl.out_hi, ck.J);
+    };
+    const WaveRole role = wave_role<C>(g, b, n, tl.lo, tl.hi);
+    if (!has_role(role)) {
+        for (int st = 0; st < nsteps; ++st) {
+            chunk_step_plain<T, C, true, false>(ck, g, er, hl);
+            post(st);
+        }
+    } else {
+        WaveProbes wp;
+        wp.n = 0;
+        run_role<T, C, true, false>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0, er, hl,
+                                    post);
+    }
+}
+
+template <typename T>
+void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_bytes, const Tile *tiles,
+                  int64_t ntiles, int nsteps, int slot0, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_trace<T, kTraceCells / 64>), dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, g, seg,
+                       slot_bytes, arr_bytes, tiles, ntiles, nsteps, slot0);
+}
+
+template void launch_trace<float>(const Grids &, char *, int64_t, int64_t, const Tile *, int64_t, int, int,
+                                  hipStream_t);
+template void launch_trace<double>(const Grids &, char *, int64_t, int64_t, const Tile *, int64_t, int, int,
+                                   hipStream_t);
+
+// ------------------------------------------------------------ reverse
+
+// Transposed steps of the adjoint on register tiles: lane holds C nodes of
+// lambda_E, lambda_H, lambda_J (storage precision, as between the steps of
+// the per-step kernel), the eleven coefficient and derivative values and the
+// gradient of its nodes (FP64).  Reverse step m (lambda^{m+1} -> lambda^m),
+// for interior nodes k, with es the adjoint of the E update's input, lHn the
+// adjoint of H^{m+1/2}:
+//   lEp = lambda_E (+ dL/dE^{m+1} at the probe node)
+//   es  = lEp (+ cm lEp(0) at node 1, + cm lEp(n-1) at node n-2, Mur) + b2 lambda_J
+//   lHn = lambda_H + CH(k+1) es(k+1) [k+1 <= n-2] - CH(k) es(k) [k >= 1]
+//   lambda_J' = a lambda_J - CJ es
+//   lambda_E' = CA es + b1 lambda_J + ch (lHn(k) - lHn(k-1)) (+ lEp(0) at 1, + lEp(n-1) at n-2)
+//   grad += es (dCA E^m - dCJ J^m - dCH curl H^{m+1/2}) + lambda_J (db1 E^m + db2 E^{m+1})
+// and at the end nodes lambda_E' = -cm lEp(k) +- ch lHn (Mur) or 0 (PEC).
+// The expressions and their order are those of the per-step kernel, so the
+// two give the same bits.  The stencil radius is one node per step, as in
+// the forward step, so a tile with a kAdjHalo halo runs up to kAdjHalo steps.
+// ROLE: the tile holds a grid end or the probe node (conditions evaluated per
+// node); otherwise every held node is interior.
+template <typename T, int C, bool ROLE>
+__device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs<T> &a, const Tile &tl, int b,
+                                               int64_t off, int64_t n, int64_t k0, int lane, int64_t mtop,
+                                               int nsteps, T (&lE)[C], T (&lH)[C], T (&lJ)[C],
+                                               double (&gr)[C])
+{
+    const int64_t tot = a.total;
+    double CA[C], CJ[C], CH[C], CHn[C], A[C], B1[C], B2[C], dCA[C], dCJ[C], dCH[C], dB1[C], dB2[C];
+    load_chunk<double, C>(a.tab + 0 * tot + off, k0, tl.hi, CA);
+    load_chunk<double, C>(a.tab + 1 * tot + off, k0, tl.hi, CJ);
+    load_chunk<double, C>(a.tab + 2 * tot + off, k0, tl.hi, CH);
+    load_chunk<double, C>(a.tab + 3 * tot + off, k0, tl.hi, A);
+    load_chunk<double, C>(a.tab + 4 * tot + off, k0, tl.hi, B1);
+    load_chunk<double, C>(a.tab + 5 * tot + off, k0, tl.hi, B2);
+    load_chunk<double, C>(a.tab + 6 * tot + off, k0, tl.hi, dCA);
+    load_chunk<double, C>(a.tab + 7 * tot + off, k0, tl.hi, dCJ);
+    load_chunk<double, C>(a.tab + 8 * tot + off, k0, tl.hi, dCH);
+    load_chunk<double, C>(a.tab + 9 * tot + off, k0, tl.hi, dB1);
+    load_chunk<double, C>(a.tab + 10 * tot + off, k0, tl.hi, dB2);
+    {
+        const double nx = shfl_down1(CH[0]);
+#pragma unroll
+        for (int i = 0; i < C; ++i) CHn[i] = (i + 1 < C) ? CH[i + 1] : nx;
+    }
+    const bool mur = g.bc == 0;
+    const double cm = g.cm, ch = g.ch;
+    // the probe node, if this tile holds it (wave-uniform)
+    const int64_t pc = g.probe[(int64_t)b * g.P + a.probe];
+    const bool has_p = ROLE && pc >= tl.lo && pc < tl.hi;
+    const int p_lane = uniform(has_p ? (pc - tl.lo) / C : -1), p_reg = uniform(has_p ? (pc - tl.lo) % C : 0);
+    const int nn = (int)n;
+    auto slotp = [&](int64_t m, int q) { return a.seg + (m - a.m0) * a.slot_bytes + q * a.arr_bytes; };
+    // forward states E^m, J^m, H^{m+1/2}, E^{m+1} of the next step are loaded
+    // one step ahead (E^{m+1} of step m-1 is this step's E^m)
+    T ne0[C], nhh[C], ne1[C];
+    double nj0[C];
+    load_chunk<T, C>((const T *)slotp(mtop, 0) + off, k0, tl.hi, ne0);
+    load_chunk<double, C>((const double *)slotp(mtop, 2) + off, k0, tl.hi, nj0);
+    load_chunk<T, C>((const T *)slotp(mtop + 1, 1) + off, k0, tl.hi, nhh);
+    load_chunk<T, C>((const T *)slotp(mtop + 1, 0) + off, k0, tl.hi, ne1);
+    for (int st = 0; st < nsteps; ++st) {
+        const int64_t m = mtop - st;
+        T e0[C], hh[C], e1[C];
+        double j0[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            e0[i] = ne0[i];
+            j0[i] = nj0[i];
+            hh[i] = nhh[i];
+            e1[i] = ne1[i];
+        }
+        if (st + 1 < nsteps) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) ne1[i] = e0[i];
+            load_chunk<T, C>((const T *)slotp(m - 1, 0) + off, k0, tl.hi, ne0);
+            load_chunk<double, C>((const double *)slotp(m - 1, 2) + off, k0, tl.hi, nj0);
+            load_chunk<T, C>((const T *)slotp(m, 1) + off, k0, tl.hi, nhh);
+        }
+        const double src = has_p ? a.gsrc[(int64_t)b * a.T_ + m] : 0.0;
+        double lEp[C], es[C], lHn[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const double l = (double)lE[i];
+            lEp[i] = (ROLE && lane == p_lane && i == p_reg) ? l + src : l;
+        }
+        double lEp0 = 0.0, lEpN = 0.0;
+        if constexpr (ROLE) {
+            // lEp at node 0 for node 1 (same lane: node 0 sits in register 0
+            // or 1 of lane 0), at node n-1 for node n-2 (same lane, or the
+            // next lane's register 0)
+            const int r0 = uniform(tl.lo <= 0 ? -tl.lo : 0);
+            lEp0 = upick<double, C>(lEp, r0);
+            const int64_t pr = n - 1 - tl.lo;
+            const int rr = uniform(pr >= 0 && pr < 64LL * C ? pr % C : 1);
+            const double nx = shfl_down1(lEp[0]);
+            const double own = upick<double, C>(lEp, rr);
+            lEpN = (rr > 0) ? own : nx;
+        }
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            double s = lEp[i];
+            if constexpr (ROLE) {
+                const int k = (int)(k0 + i);
+                s = (mur && k == 1) ? s + cm * lEp0 : s;
+                s = (mur && k == nn - 2) ? s + cm * lEpN : s;
+            }
+            es[i] = s + B2[i] * (double)lJ[i];
+        }
+        const double esn = shfl_down1(es[0]);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const double en = (i + 1 < C) ? es[i + 1] : esn;
+            double s = (double)lH[i];
+            if constexpr (ROLE) {
+                const int k = (int)(k0 + i);
+                s = (k + 1 <= nn - 2) ? s + CHn[i] * en : s;
+                s = (k >= 1) ? s - CH[i] * es[i] : s;
+            } else {
+                s += CHn[i] * en;
+                s -= CH[i] * es[i];
+            }
+            lHn[i] = s;
+        }
+        const double lHp = shfl_up1(lHn[C - 1]);
+        const T hhp = shfl_up1(hh[C - 1]);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const double lhm = (i > 0) ? lHn[i - 1] : lHp;
+            const double lj = (double)lJ[i];
+            double nJ = A[i] * lj - CJ[i] * es[i];
+            double nE = CA[i] * es[i] + B1[i] * lj + ch * (lHn[i] - lhm);
+            const double curl = (double)hh[i] - (double)((i > 0) ? hh[i - 1] : hhp);
+            const double e0d = (double)e0[i], e1d = (double)e1[i];
+            const double gnew =
+                gr[i] + (es[i] * (dCA[i] * e0d - dCJ[i] * j0[i] - dCH[i] * curl) + lj * (dB1[i] * e0d + dB2[i] * e1d));
+            if constexpr (ROLE) {
+                const int k = (int)(k0 + i);
+                nE = (mur && k == 1) ? nE + lEp0 : nE;
+                nE = (mur && k == nn - 2) ? nE + lEpN : nE;
+                const bool end = k == 0 || k == nn - 1;
+                const double nEe = mur ? -cm * lEp[i] + (k == 0 ? ch * lHn[i] : -ch * lhm) : 0.0;
+                nE = end ? nEe : nE;
+                nJ = end ? 0.0 : nJ;
+                gr[i] = (k >= 1 && k <= nn - 2) ? gnew : gr[i];
+            } else {
+                gr[i] = gnew;
+            }
+            lE[i] = (T)nE;
+            lJ[i] = (T)nJ;
+            lH[i] = (T)lHn[i];
+        }
+    }
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_adj_tiled(Grids g, AdjTileArgs<T> a, const Tile *tiles, int64_t ntiles,
+                                                   int64_t mtop, int nsteps)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t t = blk * (blockDim.x >> 6) + uniform(threadIdx.x >> 6);
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    const int b = tl.grid;
+    const int64_t off = g.off[b], n = g.n[b];
+    const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
+    T lE[C], lH[C], lJ[C];
+    double gr[C];
+    load_chunk<T, C>(a.lE + off, k0, tl.hi, lE);
+    load_chunk<T, C>(a.lH + off, k0, tl.hi, lH);
+    load_chunk<T, C>(a.lJ + off, k0, tl.hi, lJ);
+    load_chunk<double, C>(a.grad + off, k0, tl.hi, gr);
+    const int64_t pc = g.probe[(int64_t)b * g.P + a.probe];
+    const bool role = tl.lo <= 0 || tl.hi >= n || (pc >= tl.lo && pc < tl.hi);
+    if (role)
+        adj_tile_steps<T, C, true>(g, a, tl, b, off, n, k0, lane, mtop, nsteps, lE, lH, lJ, gr);
+    else
+        adj_tile_steps<T, C, false>(g, a, tl, b, off, n, k0, lane, mtop, nsteps, lE, lH, lJ, gr);
+    store_chunk<T, C>(a.nE + off, k0, tl.out_lo, tl.out_hi, lE);
+    store_chunk<T, C>(a.nH + off, k0, tl.out_lo, tl.out_hi < n ? tl.out_hi : n - 1, lH);
+    store_chunk<T, C>(a.nJ + off, k0, tl.out_lo, tl.out_hi, lJ);
+    store_chunk<double, C>(a.grad + off, k0, tl.out_lo, tl.out_hi, gr);
+}
+
+template <typename T>
+void launch_adj_tiled(const Grids &g, const AdjTileArgs<T> &a, const Tile *tiles, int64_t ntiles, int64_t mtop,
+                      int nsteps, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_adj_tiled<T, kAdjCells / 64>), dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st, g,
+                       a, tiles, ntiles, mtop, nsteps);
+}
+
+template void launch_adj_tiled<float>(const Grids &, const AdjTileArgs<float> &, const Tile *, int64_t, int64_t,
+                                      int, hipStream_t);
+template void launch_adj_tiled<double>(const Grids &, const AdjTileArgs<double> &, const Tile *, int64_t, int64_t,
+                                       int, hipStream_t);
 
 }  // namespace fdtdp

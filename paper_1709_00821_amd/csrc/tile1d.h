@@ -1,0 +1,535 @@
+// Register-tile building blocks of the 1D kernels (gfx950): each lane holds
+// C consecutive nodes of E, H (and J, coefficients in plasma, psi in CPML
+// layers) in VGPRs; a wave holds 64*C consecutive nodes.  One time step
+// needs two neighbour values per lane, moved with cross-lane DPP.  Used by
+// the forward tile and resident kernels (blocked1d.hip) and the adjoint
+// recompute and reverse kernels (adjoint1d.hip).
+#ifndef FDTDP_TILE1D_H
+#define FDTDP_TILE1D_H
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace fdtdp {
+
+// ------------------------------------------------------------ chunk state
+
+template <typename T, int C, bool PLASMA, bool CPML>
+struct Chunk {
+    T E[C], H[C];
+    double J[PLASMA ? C : 1];      // the current, held in FP64
+    double Ed[PLASMA ? C : 1];     // E^n widened to FP64 (the J update's E_old), kept across steps
+    NodeCoef<T> cf[PLASMA ? C : 1];
+    uint32_t pmask;                // bit i: node i is plasma
+    T pE[CPML ? C : 1], pH[CPML ? C : 1];
+    T bE[CPML ? C : 1], aE[CPML ? C : 1], bH[CPML ? C : 1], aH[CPML ? C : 1];
+    uint32_t eZone, hZone;         // bit i: node i has an E / H psi
+};
+
+template <typename T>
+struct BitsOf;
+template <>
+struct BitsOf<float> {
+    using type = uint32_t;
+};
+template <>
+struct BitsOf<double> {
+    using type = uint64_t;
+};
+
+// Value of v[i] for a runtime i in [0, C) (0 bits if none matches).  Written
+// as an OR of masked bit patterns: a chain of value selects would be folded
+// into one load through a selected address, which forces the register array
+// into scratch memory.
+template <typename T, int C>
+__device__ __forceinline__ T pick(const T (&v)[C], int i)
+{
+    using U = typename BitsOf<T>::type;
+    U r = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) r |= (i == j) ? __builtin_bit_cast(U, v[j]) : (U)0;
+    return __builtin_bit_cast(T, r);
+}
+
+// a if c else b, without a select between two loads (see pick)
+template <typename T>
+__device__ __forceinline__ T choose(bool c, T a, T b)
+{
+    using U = typename BitsOf<T>::type;
+    const U m = c ? ~(U)0 : (U)0;
+    return __builtin_bit_cast(T, (U)((__builtin_bit_cast(U, a) & m) | (__builtin_bit_cast(U, b) & ~m)));
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void put(T (&v)[C], int i, T x)
+{
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+        if (i == j) v[j] = x;
+}
+
+// Whole-wave neighbour moves with DPP (gfx9 wave_shl:1 / wave_shr:1): lane i
+// receives lane i+1's value (down) or lane i-1's (up); the lane with no source
+// receives 0.  One v_mov_b32_dpp per 32-bit half, no LDS crossbar trip.
+__device__ __forceinline__ int dpp_down1(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_up1(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float shfl_down1(float x)
+{
+    return __builtin_bit_cast(float, dpp_down1(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ float shfl_up1(float x)
+{
+    return __builtin_bit_cast(float, dpp_up1(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double shfl_down1(double x)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(dpp_down1(v.x), dpp_down1(v.y)));
+}
+__device__ __forceinline__ double shfl_up1(double x)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(dpp_up1(v.x), dpp_up1(v.y)));
+}
+
+// Load nodes [k0, k0+C) of array a (grid-local pointer); nodes >= lim read 0.
+template <typename T, int C>
+__device__ __forceinline__ void load_chunk(const T *a, int64_t k0, int64_t lim, T (&v)[C])
+{
+    constexpr int per16 = 16 / (int)sizeof(T);
+    if (k0 >= 0 && k0 + C <= lim && (k0 % per16) == 0) {
+        constexpr int per = per16;
+        static_assert(C % per == 0, "C must fill 16-byte vectors");
+        const uint4 *p = reinterpret_cast<const uint4 *>(a + k0);
+#pragma unroll
+        for (int q = 0; q < C / per; ++q) {
+            const uint4 u = p[q];
+            const T *t = reinterpret_cast<const T *>(&u);
+#pragma unroll
+            for (int r = 0; r < per; ++r) v[q * per + r] = t[r];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < C; ++i) v[i] = (k0 + i < lim && k0 + i >= 0) ? a[k0 + i] : (T)0;
+    }
+}
+
+// Store nodes [k0, k0+C) restricted to [lo, hi).
+template <typename T, int C>
+__device__ __forceinline__ void store_chunk(T *a, int64_t k0, int64_t lo, int64_t hi, const T (&v)[C])
+{
+    constexpr int per16 = 16 / (int)sizeof(T);
+    if (k0 >= lo && k0 + C <= hi && (k0 % per16) == 0) {
+        constexpr int per = per16;
+        uint4 *p = reinterpret_cast<uint4 *>(a + k0);
+#pragma unroll
+        for (int q = 0; q < C / per; ++q) {
+            uint4 u;
+            T *t = reinterpret_cast<T *>(&u);
+#pragma unroll
+            for (int r = 0; r < per; ++r) t[r] = v[q * per + r];
+            p[q] = u;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            if (k0 + i >= lo && k0 + i < hi) a[k0 + i] = v[i];
+    }
+}
+
+// Load the lane's chunk starting at grid node k0 of grid b (buffer `buf`).
+template <typename T, int C, bool PLASMA, bool CPML>
+__device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+                                           const State<T> &s, int buf, int b, int64_t off,
+                                           int64_t n, int64_t k0, int64_t lim)
+{
+    load_chunk<T, C>(s.E[buf] + off, k0, lim, ck.E);
+    load_chunk<T, C>(s.H[buf] + off, k0, lim, ck.H);
+    ck.pmask = 0;
+    if constexpr (PLASMA) {
+        load_chunk<double, C>(s.J[buf] + off, k0, lim, ck.J);
+#pragma unroll
+        for (int i = 0; i < C; ++i) ck.Ed[i] = (double)ck.E[i];
+        double w[C], v[C];
+        load_chunk<double, C>(g.wp2 + off, k0, lim, w);
+        load_chunk<double, C>(g.nu + off, k0, lim, v);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            if (w[i] != 0.0) ck.pmask |= 1u << i;
+            ck.cf[i] = node_coef_t<T>(w[i], v[i], g.dt, g.dz, g.scheme);
+        }
+    }
+    if constexpr (CPML) {
+        ck.eZone = ck.hZone = 0;
+        const int P = g.cpmlP;
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int64_t k = k0 + i;
+            ck.pE[i] = ck.pH[i] = (T)0;
+            ck.bE[i] = ck.bH[i] = (T)1;
+            ck.aE[i] = ck.aH[i] = (T)0;
+            if (k < 0 || k >= lim) continue;   // k = -1: a tile shifted off node 0
+            int slot = -1, tab = 0;
+            // E psi: nodes 1..P-1 and n-P..n-2 (depth d -> table d-1)
+            if (k >= 1 && k < P) { tab = P - 1 - (int)k; slot = (int)k; }
+            else if (k > n - 1 - P && k <= n - 2) { tab = (int)(k - (n - 1 - P)) - 1; slot = P + (int)(k - (n - P)); }
+            if (slot >= 0) {
+                ck.eZone |= 1u << i;
+                ck.pE[i] = s.psiE[buf][(int64_t)b * 2 * P + slot];
+                ck.bE[i] = (T)g.cpml[tab];
+                ck.aE[i] = (T)g.cpml[P + tab];
+            }
+            slot = -1;
+            // H psi: nodes 0..P-1 and n-1-P..n-2 (depth j+1/2 -> table j)
+            if (k < P) { tab = P - 1 - (int)k; slot = (int)k; }
+            else if (k >= n - 1 - P && k <= n - 2) { tab = (int)(k - (n - 1 - P)); slot = P + tab; }
+            if (slot >= 0) {
+                ck.hZone |= 1u << i;
+                ck.pH[i] = s.psiH[buf][(int64_t)b * 2 * P + slot];
+                ck.bH[i] = (T)g.cpml[2 * P + tab];
+                ck.aH[i] = (T)g.cpml[3 * P + tab];
+            }
+        }
+    }
+}
+
+template <typename T, int C, bool PLASMA, bool CPML>
+__device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+                                            const State<T> &s, int buf, int b, int64_t off,
+                                            int64_t n, int64_t k0, int64_t lo, int64_t hi)
+{
+    store_chunk<T, C>(s.E[buf] + off, k0, lo, hi, ck.E);
+    store_chunk<T, C>(s.H[buf] + off, k0, lo, hi < n ? hi : n - 1, ck.H);   // H has n-1 nodes
+    if constexpr (PLASMA) store_chunk<double, C>(s.J[buf] + off, k0, lo, hi, ck.J);
+    if constexpr (CPML) {
+        const int P = g.cpmlP;
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int64_t k = k0 + i;
+            if (k < lo || k >= hi) continue;
+            if (ck.eZone & (1u << i)) {
+                const int slot = (k < P) ? (int)k : P + (int)(k - (n - P));
+                s.psiE[buf][(int64_t)b * 2 * P + slot] = ck.pE[i];
+            }
+            if (ck.hZone & (1u << i)) {
+                const int slot = (k < P) ? (int)k : P + (int)(k - (n - 1 - P));
+                s.psiH[buf][(int64_t)b * 2 * P + slot] = ck.pH[i];
+            }
+        }
+    }
+}
+
+// H^{n+1/2} of the chunk; Er = E of the next node after the chunk.
+template <typename T, int C, bool PLASMA, bool CPML>
+__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er, T ch)
+{
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const T er = (i + 1 < C) ? ck.E[i + 1] : Er;
+        if constexpr (CPML) {
+            if (ck.hZone & (1u << i)) {
+                const T dE = er - ck.E[i];
+                ck.pH[i] = fmat(ck.aH[i], dE, ck.bH[i] * ck.pH[i]);
+                ck.H[i] = fmat(-ch, dE + ck.pH[i], ck.H[i]);
+                continue;
+            }
+        }
+        ck.H[i] = h_update<T>(ck.H[i], ck.E[i], er, ch);
+    }
+}
+
+// E^{n+1} (before the source) of the chunk; Hl = H of the node before the
+// chunk.
+template <typename T, int C, bool PLASMA, bool CPML>
+__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T ce)
+{
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        T curl = ck.H[i] - ((i > 0) ? ck.H[i - 1] : Hl);
+        if constexpr (CPML) {
+            if (ck.eZone & (1u << i)) {
+                ck.pE[i] = fmat(ck.aE[i], curl, ck.bE[i] * ck.pE[i]);
+                curl = curl + ck.pE[i];
+            }
+        }
+        if constexpr (PLASMA) {
+            // the plasma formula reproduces the vacuum update at vacuum nodes
+            ck.E[i] = e_update_plasma(ck.E[i], ck.J[i], curl, ck.cf[i]);
+        } else {
+            ck.E[i] = e_update_vac<T>(ck.E[i], curl, ce);
+        }
+    }
+}
+
+// J update of the chunk (after the source), with E_old the FP64 copy of E^n
+// kept from the previous step; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.
+// The Mur ends rewrite E after this and leave their copy stale, which is
+// harmless: end nodes carry no plasma (b1 = 0).
+template <typename T, int C, bool PLASMA, bool CPML>
+__device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML> &ck)
+{
+    if constexpr (PLASMA) {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const double en = (double)ck.E[i];
+            ck.J[i] = j_update<T>(ck.J[i], ck.Ed[i], en, ck.cf[i]);
+            ck.Ed[i] = en;
+        }
+    }
+}
+
+// One time step of a chunk that holds no grid end and no source: H, E, J only.
+template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
+__device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+                                                 GetEr get_er, GetHl get_hl)
+{
+    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
+    chunk_j<T, C, PLASMA, CPML>(ck);
+}
+
+// Where a grid's special nodes sit in one wave's span of 64*C nodes: a
+// node at position pos from the wave's first node is register pos % C of
+// lane pos / C.  The values are the same in every lane (read through
+// readfirstlane), so the register selects below run on scalar conditions.
+// A lane of -1 means the wave does not hold the node.
+struct WaveRole {
+    int src_lane, src_reg;       // the source node
+    int left_lane, left_reg;     // node 0: lane 0, register 0 or 1 (a wave never starts left of node -1)
+    int right_lane, right_reg;   // node n-1: never register 0 of lane 0 (see the tile builder)
+};
+
+__device__ __forceinline__ int uniform(int64_t v) { return __builtin_amdgcn_readfirstlane((int)v); }
+
+template <int C>
+__device__ __forceinline__ WaveRole wave_role(const Grids &g, int b, int64_t n, int64_t wave_lo, int64_t wave_hi)
+{
+    const int64_t s = g.src[b];
+    const int64_t ps = (s >= 0 && s >= wave_lo && s < wave_hi) ? s - wave_lo : -1;
+    const int64_t pl = (wave_lo <= 0 && 0 < wave_hi) ? -wave_lo : -1;
+    const int64_t pr = (n - 1 >= wave_lo && n - 1 < wave_hi) ? n - 1 - wave_lo : -1;
+    WaveRole r;
+    r.src_lane = uniform(ps >= 0 ? ps / C : -1);
+    r.src_reg = uniform(ps >= 0 ? ps % C : 0);
+    r.left_lane = uniform(pl >= 0 ? 0 : -1);
+    r.left_reg = uniform(pl >= 0 ? pl : 0);
+    r.right_lane = uniform(pr >= 0 ? pr / C : -1);
+    r.right_reg = uniform(pr >= 0 ? pr % C : 1);
+    return r;
+}
+
+__device__ __forceinline__ bool has_role(const WaveRole &r)
+{
+    return r.src_lane >= 0 || r.left_lane >= 0 || r.right_lane >= 0;
+}
+
+// v[i] for a wave-uniform i in [0, C).  The registers are gathered into one
+// vector value and indexed there, which gfx950 code generation turns into
+// C - 1 selects on scalar conditions.  (Selecting between the array elements
+// directly would be folded into one load through a selected address and force
+// the array into scratch memory.)
+template <typename T, int C>
+__device__ __forceinline__ T upick(const T (&v)[C], int i)
+{
+    typedef T vec __attribute__((ext_vector_type(C)));
+    vec x;
+#pragma unroll
+    for (int j = 0; j < C; ++j) x[j] = v[j];
+    return x[i];
+}
+
+// v[i] = x in the lanes where `here` holds (i wave-uniform).
+template <typename T, int C>
+__device__ __forceinline__ void uput(T (&v)[C], int i, bool here, T x)
+{
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = (here && i == j) ? x : v[j];
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(v.x, l),
+                                                __builtin_amdgcn_readlane(v.y, l)));
+}
+
+// The end values the Mur updates read, E^n at nodes 0, 1 and n-1, n-2, held
+// from one step to the next: each equals what the previous step wrote (the
+// end node) or read (its neighbour, which later sub-steps of that step leave
+// alone).  Meaningful only in the lane holding the end.
+template <typename T>
+struct EndCarry {
+    T e0, e1, eR, eR1;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, EndCarry<T> &c)
+{
+    c.e0 = r.left_reg ? E[1] : E[0];
+    c.e1 = r.left_reg ? E[2] : E[1];
+    const int ir = r.right_reg;
+    c.eR = upick<T, C>(E, ir);
+    c.eR1 = ir ? upick<T, C>(E, ir - 1) : shfl_up1(E[C - 1]);
+}
+
+// One full time step of a wave holding a grid end, the source or a probe: H,
+// E, the source (added to E^{n+1}, eq.(15), before the J update), J, then the
+// ends (first-order Mur, or PEC E = 0).  sv: the source value of this step.
+// Every part runs in every such wave, as selects whose lane condition is
+// false where the wave does not hold the node: no branch, so the registers
+// need no merging copies.
+template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
+__device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+                                           const WaveRole &r, int lane, EndCarry<T> &c, double sv,
+                                           GetEr get_er, GetHl get_hl)
+{
+    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
+    uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
+    chunk_j<T, C, PLASMA, CPML>(ck);
+    const bool mur = g.bc == 0;
+    {
+        const T en1 = r.left_reg ? ck.E[2] : ck.E[1];
+        const T v = mur ? (T)(c.e1 + (T)g.cm * (en1 - c.e0)) : (T)0;
+        const bool here = lane == r.left_lane;
+        ck.E[0] = (here && !r.left_reg) ? v : ck.E[0];
+        ck.E[1] = (here && r.left_reg) ? v : ck.E[1];
+        c.e0 = v;
+        c.e1 = en1;
+    }
+    {
+        const int ir = r.right_reg;
+        const T prev = shfl_up1(ck.E[C - 1]);
+        const T left1 = upick<T, C>(ck.E, ir > 0 ? ir - 1 : 0);
+        const T en1 = ir > 0 ? left1 : prev;
+        const T v = mur ? (T)(c.eR1 + (T)g.cm * (en1 - c.eR)) : (T)0;
+        uput<T, C>(ck.E, ir, lane == r.right_lane, v);
+        c.eR = v;
+        c.eR1 = en1;
+    }
+}
+
+
+
+// The probes a wave samples: those of grid b at nodes in [lo, hi) (inside
+// the wave's span).  The first two are kept as wave-uniform lane, register
+// and sample-row offset; a wave with more walks the probe list every step.
+struct WaveProbes {
+    int n;                 // probes in range
+    int lane[2], reg[2];   // where the probe node sits in the wave
+    int64_t row[2];        // (b * P + p) * SB: the probe's row of the sample buffer
+};
+
+template <int C>
+__device__ __forceinline__ WaveProbes wave_probes_find(const Grids &g, int b, int64_t wave_lo, int64_t lo,
+                                                      int64_t hi)
+{
+    int n = 0;
+    int64_t q0 = 0, q1 = 0, r0 = 0, r1 = 0;
+    for (int p = 0; p < g.P; ++p) {
+        const int64_t q = g.probe[(int64_t)b * g.P + p];
+        if (q >= lo && q < hi) {
+            const int64_t row = ((int64_t)b * g.P + p) * g.SB;
+            if (n == 0) { q0 = q - wave_lo; r0 = row; }
+            if (n == 1) { q1 = q - wave_lo; r1 = row; }
+            ++n;
+        }
+    }
+    WaveProbes w;
+    w.n = uniform(n);
+    w.lane[0] = uniform(q0 / C);
+    w.reg[0] = uniform(q0 % C);
+    w.lane[1] = uniform(q1 / C);
+    w.reg[1] = uniform(q1 % C);
+    w.row[0] = (int64_t)__builtin_amdgcn_readfirstlane((int)r0) |
+               ((int64_t)__builtin_amdgcn_readfirstlane((int)(r0 >> 32)) << 32);
+    w.row[1] = (int64_t)__builtin_amdgcn_readfirstlane((int)r1) |
+               ((int64_t)__builtin_amdgcn_readfirstlane((int)(r1 >> 32)) << 32);
+    return w;
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void wave_probe_store(const Grids &g, int lane_p, int reg, int64_t row, int lane,
+                                                 const T (&E)[C], int slot)
+{
+    const T v = upick<T, C>(E, reg);
+    if (lane == lane_p) g.samp[row + slot] = (double)v;
+}
+
+// Samples of one step (after the step's ends), one store per probe: the
+// path for a wave that holds more than two probes.
+template <typename T, int C>
+__device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_lo, int64_t lo, int64_t hi,
+                                            int lane, const T (&E)[C], int slot)
+{
+    for (int p = 0; p < g.P; ++p) {
+        const int64_t q = g.probe[(int64_t)b * g.P + p];
+        if (q >= lo && q < hi) {
+            const int pos = uniform(q - wave_lo);
+            wave_probe_store<T, C>(g, pos / C, pos % C, ((int64_t)b * g.P + p) * g.SB, lane, E, slot);
+        }
+    }
+}
+
+// nsteps full steps of a wave that holds a grid end, the source or a probe
+// (sample slots slot0 .. slot0 + nsteps - 1 of the window), in runs of up to
+// 64 steps.  The only load is at the start of a run: the source values of its
+// steps, one per lane of the window's table, broadcast from lane st.  Inside a
+// run the wave issues nothing but the probe stores, which it never waits on.
+// (Every cross-lane read here takes a value all lanes computed: a value
+// computed only in some lanes would be stale in the lane that is read.)
+template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl, typename Post>
+__device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g, const WaveRole &r,
+                                         const WaveProbes &wp, int lane, int b, int64_t wave_lo, int64_t plo,
+                                         int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
+{
+    EndCarry<T> c;
+    ends_init<T, C>(ck.E, r, c);
+    for (int base = 0; base < nsteps; base += 64) {
+        const int cnt = nsteps - base < 64 ? nsteps - base : 64;
+        const int slot = slot0 + base;
+        double svl = 0.0;
+        if (r.src_lane >= 0) {
+            const int i = slot + lane;
+            svl = g.srcv[i < g.SB ? i : g.SB - 1];
+        }
+        auto one = [&](int st) {
+            const double sv = (r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
+            chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
+            post(base + st);
+            if (wp.n > 2) {
+                wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
+            } else {
+                if (wp.n > 0) wave_probe_store<T, C>(g, wp.lane[0], wp.reg[0], wp.row[0], lane, ck.E, slot + st);
+                if (wp.n > 1) wave_probe_store<T, C>(g, wp.lane[1], wp.reg[1], wp.row[1], lane, ck.E, slot + st);
+            }
+        };
+        int st = 0;
+        for (; st + 2 <= cnt; st += 2) {
+            one(st);
+            one(st + 1);
+        }
+        if (st < cnt) one(st);
+    }
+}
+
+// Block index remapped so that each XCD (workgroups are dealt round-robin to
+// the 8 XCDs) receives a contiguous range of tiles and neighbouring tiles
+// share an L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk)
+{
+    const int64_t q = nblk / 8, r = nblk % 8;
+    const int64_t x = bid % 8, j = bid / 8;
+    return x * q + (x < r ? x : r) + j;
+}
+
+
+}  // namespace fdtdp
+#endif
