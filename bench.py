@@ -170,6 +170,57 @@ def adjoint_leg(precision="f32"):
             "forward_steps_per_pass": tune["steps_per_pass"]}
 
 
+# GPU times (ms) of the paper's timing table (Table 2): 1000 steps of the
+# plasma-slab setup at each cell count, on the GeForce GTX 1080 it names, and
+# the serial CPU program's times on its Core i7-6700.  Context only.
+PAPER_TABLE2_MS = {1024: (33, 279), 5120: (33, 379), 10240: (33, 504), 20480: (34, 753), 30720: (46, 982),
+                   40960: (53, 1231), 51200: (61, 1467), 61440: (64, 1701)}
+
+
+def table2_leg(precision="f64", reps=5, serial_cells=10240):
+    """The paper's timing experiment on this GPU: 1000 steps of its slab setup
+    at each cell count of its Table 2 (FP64: the paper states no precision),
+    launch shape from the tuner; beside it the paper's GTX 1080 times and, for
+    one size, the serial oracle on this host (the paper's serial column)."""
+    import torch
+    import oracle
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd import tune as TU
+    from paper_1709_00821_amd.plasma import FdtdPlasma
+    T = 1000
+    rows = []
+    for n, (gpu_ms, ser_ms) in PAPER_TABLE2_MS.items():
+        p = W.paper_preset(steps=T, n=n)
+        tune = TU.pick(precision, n)
+        with FdtdPlasma(p, precision=precision, exec="auto", **tune) as h:
+            h.run(T)
+            h.synchronize()
+            times = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(h.stream)
+                h.run(T)
+                e1.record(h.stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[len(times) // 2]
+        rows.append({"cells": n, "ms": round(ms, 4), "mcells": round(n * T / ms / 1e3, 1),
+                     "paper_gtx1080_ms": gpu_ms, "paper_gtx1080_mcells": round(n * T / gpu_ms / 1e3, 1),
+                     "vs_paper_gpu": round(gpu_ms / ms, 1)})
+        log(f"bench: table-2 size {n}: {ms:.3f} ms (paper GPU {gpu_ms} ms)")
+    p = W.paper_preset(steps=T, n=serial_cells)
+    t0 = time.perf_counter()
+    oracle.run(p, T)
+    ser = (time.perf_counter() - t0) * 1e3
+    gpu = next(r["ms"] for r in rows if r["cells"] == serial_cells)
+    return {"context": "paper Table 2 setup, 1000 steps; paper numbers are its own hardware's, not targets",
+            "precision": precision, "rows": rows,
+            "serial_oracle_ms_at": {"cells": serial_cells, "ms": round(ser, 1), "cores": 1,
+                                    "speedup_gpu_vs_serial": round(ser / gpu, 1),
+                                    "paper_speedup_gpu_vs_serial": round(PAPER_TABLE2_MS[serial_cells][1] /
+                                                                         PAPER_TABLE2_MS[serial_cells][0], 2)}}
+
+
 def c1_leg(reps=5):
     """The 1000-cell slab (latency bound: the state fits one CU)."""
     import torch
@@ -326,7 +377,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=60)
-    ap.add_argument("--only", choices=["c3", "batched", "adjoint", "c1"],
+    ap.add_argument("--only", choices=["c3", "batched", "adjoint", "c1", "table2"],
                     help="run just this leg and print its JSON (profiling runs)")
     ap.add_argument("--c3-steps", type=int, default=2000)
     args = ap.parse_args()
@@ -354,7 +405,7 @@ def main():
         del x, y
     if args.only:
         leg = {"c3": lambda: c3_leg(T=args.c3_steps), "batched": batched_leg, "adjoint": adjoint_leg,
-               "c1": c1_leg}[args.only]
+               "c1": c1_leg, "table2": table2_leg}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     from paper_1709_00821_amd import workloads as W
@@ -410,6 +461,7 @@ def main():
         out["adjoint"]["vs_plain"] = round(out["adjoint"]["value"] / out["value"], 4)
         out["c1_latency"] = c1_leg()
         out["c3_3d"] = c3_leg()
+        out["paper_table2"] = table2_leg()
     if not args.no_check:
         log("bench: oracle spectra on the source's light cone (exact)")
         t0 = time.perf_counter()

@@ -87,17 +87,22 @@ def slab_c1(n: int = 1000, dz: float = 75e-6, slab=(400, 520),
     return _base(n, dz, dt, wp2, nuv, src, probes, freqs, bc=bc, steps=steps)
 
 
-def paper_preset(steps: int = 8192) -> Problem1D:
-    """The paper's 4096-cell domain: 1200-cell (9 cm) slab in the middle,
-    dt = 125 fs taken literally, a 5-cell absorbing layer at each end."""
-    n, dz, dt = 4096, 75e-6, 125e-15
+def paper_preset(steps: int = 8192, n: int = 4096) -> Problem1D:
+    """The paper's domain (4096 cells by default): 1200-cell (9 cm) slab in the
+    middle, dt = 125 fs taken literally, a 5-cell absorbing layer at each end,
+    source 600 cells in and probes 300 cells from the ends.  Other n (the cell
+    counts of the paper's timing table) scale source and probe positions by
+    n / 4096 and shorten the slab to n / 3 where 1200 cells do not fit."""
+    dz, dt = 75e-6, 125e-15
     wp = 2 * math.pi * 28.7 * GHZ
     wp2 = np.zeros(n)
-    lo = (n - 1200) // 2
-    wp2[lo:lo + 1200] = wp * wp
+    slab = min(1200, n // 3)
+    lo = (n - slab) // 2
+    wp2[lo:lo + slab] = wp * wp
     nuv = np.full(n, 2e10)
     freqs = np.linspace(1 * GHZ, 100 * GHZ, 256)
-    return _base(n, dz, dt, wp2, nuv, 600, (300, n - 300), freqs,
+    src = int(round(600 * n / 4096))
+    return _base(n, dz, dt, wp2, nuv, src, (src // 2, n - src // 2), freqs,
                  bc="cpml", cpml_cells=5, steps=steps)
 
 
