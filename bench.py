@@ -129,10 +129,17 @@ def batched_leg(precision="f32", n_slabs=4096, T=8000, reps=2):
     ms = e0.elapsed_time(e1) / reps
     h.close()
     log(f"bench: batched {n_slabs} slabs ({cells} nodes) x {T} steps: {ms:.2f} ms")
-    return {"value": round(cells * T / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
+    value = cells * T / (ms / 1e3) / 1e6
+    plasma = sum(int(np.count_nonzero(q.wp2)) for q in slabs)
+    ss = (plasma * algorithmic_bytes_per_node(precision, True)
+          + (cells - plasma) * algorithmic_bytes_per_node(precision, False)) / cells
+    return {"value": round(value, 1), "unit": "Mcell-updates/s",
             "ms": round(ms, 3), "slabs": n_slabs, "nodes": cells, "time_steps": T,
             "precision": precision, "exec": "auto (tiled over the concatenated slabs)",
-            "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"]}
+            "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"],
+            "single_step_equivalent": {"gbs": round(value * 1e6 * ss / 1e9, 1),
+                                       "frac_of_hbm_peak": round(value * 1e6 * ss / 1e9 / HBM_PEAK_GBS, 2),
+                                       "bytes_per_cell_update": round(ss, 2)}}
 
 
 def adjoint_leg(precision="f32"):
@@ -347,6 +354,15 @@ def cpu_baseline(p, steps):
                       f"{dt:.1f} s incl. coefficient build"}
 
 
+def vacuum_spectra(p, precision, T, tune):
+    """Probe spectra of the plasma-free run of p on the GPU (the reference run
+    of the two-run reflection and transmission)."""
+    from paper_1709_00821_amd.plasma import FdtdPlasma
+    with FdtdPlasma(p.vacuum(), precision=precision, exec="tiled", **tune) as h:
+        h.run(T)
+        return h.spectra()[0]
+
+
 def oracle_spectra_lightcone(p, T):
     """Exact oracle spectra of the full grid: outside the source's light cone
     the fields stay exactly zero for T steps, so a trimmed grid suffices."""
@@ -428,6 +444,9 @@ def main():
     rl = alu_roofline(prof, dom, tune["steps_per_pass"])
     hv = roofline(prof, args.precision)
     rl["traffic"] = hv["traffic"] = counter_traffic(dom, args.precision, tune, cells)
+    # single-step algorithmic bytes per cell-update of this workload (half plasma)
+    ss_bytes = 0.5 * algorithmic_bytes_per_node(args.precision, True) + \
+        0.5 * algorithmic_bytes_per_node(args.precision, False)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -440,9 +459,11 @@ def main():
                    "fields": args.precision, "coefficients_dft": "f64"},
         "roofline": rl,
         "hbm_view": hv,
-        "single_step_bound_mcells": round(HBM_PEAK_GBS * 1e9 / (
-            0.5 * algorithmic_bytes_per_node(args.precision, True)
-            + 0.5 * algorithmic_bytes_per_node(args.precision, False)) / 1e6, 1),
+        "single_step_bound_mcells": round(HBM_PEAK_GBS * 1e9 / ss_bytes / 1e6, 1),
+        # what a one-step-per-pass kernel would have to move to match this rate
+        "single_step_equivalent": {"gbs": round(value * 1e6 * ss_bytes / 1e9, 1),
+                                   "frac_of_hbm_peak": round(value * 1e6 * ss_bytes / 1e9 / HBM_PEAK_GBS, 2),
+                                   "bytes_per_cell_update": ss_bytes},
         "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "nodes": v[2]}
                     for k, v in prof.items()},
     }
@@ -463,14 +484,26 @@ def main():
         out["c3_3d"] = c3_leg()
         out["paper_table2"] = table2_leg()
     if not args.no_check:
-        log("bench: oracle spectra on the source's light cone (exact)")
+        log("bench: oracle spectra on the source's light cone (exact), plasma and vacuum runs")
         t0 = time.perf_counter()
         Xo = oracle_spectra_lightcone(p, T)
-        acc = {}
+        Xvo = oracle_spectra_lightcone(p.vacuum(), T)
+        osec = time.perf_counter() - t0
+        Ro, To = (Xo[0] - Xvo[0]) / Xvo[0], Xo[1] / Xvo[1]
+        acc, rerr, terr = {}, {}, {}
         for prec, r in results.items():
             acc[prec] = float(np.max(np.abs(r[1] - Xo)) / np.max(np.abs(Xo)))
-        out["accuracy"] = {"spectra_rel_err_vs_fp64_oracle": acc,
-                           "oracle_seconds": round(time.perf_counter() - t0, 1)}
+            # two-run reflection and transmission, the vacuum run at the same precision
+            Xv = vacuum_spectra(p, prec, T, r[3])
+            R, Tt = (r[1][0] - Xv[0]) / Xv[0], r[1][1] / Xv[1]
+            rerr[prec] = float(np.max(np.abs(np.abs(R) - np.abs(Ro))))
+            terr[prec] = float(np.max(np.abs(np.abs(Tt) - np.abs(To))))
+            hi = p.freqs >= 12e9
+            rerr[prec + "_f_ge_12ghz"] = float(np.max(np.abs(np.abs(R[hi]) - np.abs(Ro[hi]))))
+            terr[prec + "_f_ge_12ghz"] = float(np.max(np.abs(np.abs(Tt[hi]) - np.abs(To[hi]))))
+        out["accuracy"] = {"spectra_rel_err_vs_fp64_oracle": acc, "max_abs_R_err": rerr, "max_abs_T_err": terr,
+                           "frequencies_ghz": [round(float(p.freqs[0]) / 1e9, 3), round(float(p.freqs[-1]) / 1e9, 3)],
+                           "oracle_seconds": round(osec, 1)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)
