@@ -27,48 +27,6 @@ struct Chunk {
     uint32_t eZone, hZone;         // bit i: node i has an E / H psi
 };
 
-template <typename T>
-struct BitsOf;
-template <>
-struct BitsOf<float> {
-    using type = uint32_t;
-};
-template <>
-struct BitsOf<double> {
-    using type = uint64_t;
-};
-
-// Value of v[i] for a runtime i in [0, C) (0 bits if none matches).  Written
-// as an OR of masked bit patterns: a chain of value selects would be folded
-// into one load through a selected address, which forces the register array
-// into scratch memory.
-template <typename T, int C>
-__device__ __forceinline__ T pick(const T (&v)[C], int i)
-{
-    using U = typename BitsOf<T>::type;
-    U r = 0;
-#pragma unroll
-    for (int j = 0; j < C; ++j) r |= (i == j) ? __builtin_bit_cast(U, v[j]) : (U)0;
-    return __builtin_bit_cast(T, r);
-}
-
-// a if c else b, without a select between two loads (see pick)
-template <typename T>
-__device__ __forceinline__ T choose(bool c, T a, T b)
-{
-    using U = typename BitsOf<T>::type;
-    const U m = c ? ~(U)0 : (U)0;
-    return __builtin_bit_cast(T, (U)((__builtin_bit_cast(U, a) & m) | (__builtin_bit_cast(U, b) & ~m)));
-}
-
-template <typename T, int C>
-__device__ __forceinline__ void put(T (&v)[C], int i, T x)
-{
-#pragma unroll
-    for (int j = 0; j < C; ++j)
-        if (i == j) v[j] = x;
-}
-
 // Whole-wave neighbour moves with DPP (gfx9 wave_shl:1 / wave_shr:1): lane i
 // receives lane i+1's value (down) or lane i-1's (up); the lane with no source
 // receives 0.  One v_mov_b32_dpp per 32-bit half, no LDS crossbar trip.
