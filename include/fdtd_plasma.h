@@ -66,7 +66,8 @@ enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 
  * MIXED:    per pass, the grids that fit a workgroup run as RESIDENT bins and
  *           the longer ones as TILED tiles (Mur or PEC ends; batches of
  *           uneven slabs);
- * AUTO:     RESIDENT when every grid fits a workgroup, else TILED. */
+ * AUTO:     TILED (faster than RESIDENT on MI355X for single grids and for
+ *           batches of short grids alike). */
 enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RESIDENT = 3,
        FDTD_EXEC_MIXED = 4 };
 

@@ -426,19 +426,12 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     p.exec = d->exec;
     if ((p.exec == FDTD_EXEC_RESIDENT || p.exec == FDTD_EXEC_MIXED) && d->bc == FDTD_BC_CPML)
         return fail(FDTD_E_UNSUPPORTED, "the resident executor has no CPML ends");
-    if (p.exec == FDTD_EXEC_AUTO && d->bc == FDTD_BC_CPML) p.exec = FDTD_EXEC_TILED;
     const int64_t res_max = resident_max_nodes(p.resC, p.resWaves);
-    if (p.exec == FDTD_EXEC_AUTO) {
-        Plan q = p;
-        build_bins(d, q, true);
-        int64_t fit = 0;
-        std::vector<char> seen(d->batch, 0);
-        for (auto &s : q.slots)
-            if (s.grid >= 0 && !seen[s.grid]) { seen[s.grid] = 1; ++fit; }
-        // (MIXED is left to explicit requests: on the 4096-slab benchmark batch it
-        // is slower than tiles alone, the bins occupying whole CUs for a window)
-        p.exec = fit == d->batch ? FDTD_EXEC_RESIDENT : FDTD_EXEC_TILED;
-    }
+    // AUTO takes the register tiles: on MI355X they beat the resident bins for
+    // a single short grid and for batches of short grids alike (no per-step
+    // barriers, no idle waves), and the bins beside tiles (MIXED) lose on the
+    // 4096-slab batch; RESIDENT and MIXED stay available on request
+    if (p.exec == FDTD_EXEC_AUTO) p.exec = FDTD_EXEC_TILED;
     if (p.exec == FDTD_EXEC_RESIDENT) {
         if (!build_bins(d, p))
             return fail(FDTD_E_INVALID, "a grid exceeds %lld nodes, the resident limit", (long long)res_max);
