@@ -230,6 +230,21 @@ __device__ __forceinline__ float e_update_plasma(float E, double J, float curl,
     return fmat(-c.eH, curl, fmat(-c.eJ, (float)J, fmat(c.eA, E, E)));
 }
 
+// The same two updates with CJ and CH supplied negated (nJ = -CJ, nH = -CH):
+// bit for bit the values above, since negation is exact.  The register tiles
+// hold the coefficients this way so that every FMA is an accumulate with
+// plain register operands (no negation modifier to fold into the
+// instruction).
+__device__ __forceinline__ double e_update_plasma_neg(double E, double J, double curl, double nJ, double nH,
+                                                      double eA)
+{
+    return fmat(nH, curl, fmat(nJ, J, eA * E));
+}
+__device__ __forceinline__ float e_update_plasma_neg(float E, double J, float curl, float nJ, float nH, float eA)
+{
+    return fmat(nH, curl, fmat(nJ, (float)J, fmat(eA, E, E)));
+}
+
 // J_new = a J + b1 E_old + b2 E_new in FP64 for both field precisions: J is
 // held in FP64 (eq.(11): the exp(-nu dt) fractions and the current they
 // accumulate keep their FP64 accuracy); the E values enter already widened.

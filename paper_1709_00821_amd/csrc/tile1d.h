@@ -20,7 +20,8 @@ struct Chunk {
     T E[C], H[C];
     double J[PLASMA ? C : 1];      // the current, held in FP64
     double Ed[PLASMA ? C : 1];     // E^n widened to FP64 (the J update's E_old), kept across steps
-    NodeCoef<T> cf[PLASMA ? C : 1];
+    NodeCoef<T> cf[PLASMA ? C : 1];   // eJ and eH held negated (see chunk_load)
+    T nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
     uint32_t pmask;                // bit i: node i is plasma
     T pE[CPML ? C : 1], pH[CPML ? C : 1];
     T bE[CPML ? C : 1], aE[CPML ? C : 1], bH[CPML ? C : 1], aH[CPML ? C : 1];
@@ -102,12 +103,25 @@ __device__ __forceinline__ void store_chunk(T *a, int64_t k0, int64_t lo, int64_
     }
 }
 
+// x, hidden from the optimiser.  A coefficient negated through here reaches
+// the step's FMAs as a plain register, so they compile to the two-operand
+// accumulate form; a visible negation is folded into the three-operand form
+// as a source modifier, which issues at half the rate for FP32 on gfx950.
+template <typename T>
+__device__ __forceinline__ T opaque(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Load the lane's chunk starting at grid node k0 of grid b (buffer `buf`).
 template <typename T, int C, bool PLASMA, bool CPML>
 __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
                                            const State<T> &s, int buf, int b, int64_t off,
                                            int64_t n, int64_t k0, int64_t lim)
 {
+    ck.nch = opaque<T>(-(T)g.ch);
+    ck.nce = opaque<T>(-(T)g.ce);
     load_chunk<T, C>(s.E[buf] + off, k0, lim, ck.E);
     load_chunk<T, C>(s.H[buf] + off, k0, lim, ck.H);
     ck.pmask = 0;
@@ -122,6 +136,8 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
         for (int i = 0; i < C; ++i) {
             if (w[i] != 0.0) ck.pmask |= 1u << i;
             ck.cf[i] = node_coef_t<T>(w[i], v[i], g.dt, g.dz, g.scheme);
+            ck.cf[i].eJ = opaque<T>(-ck.cf[i].eJ);
+            ck.cf[i].eH = opaque<T>(-ck.cf[i].eH);
         }
     }
     if constexpr (CPML) {
@@ -184,9 +200,10 @@ __device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML> &ck,
     }
 }
 
-// H^{n+1/2} of the chunk; Er = E of the next node after the chunk.
+// H^{n+1/2} of the chunk; Er = E of the next node after the chunk.  (The
+// update of h_update, with the coefficient held negated.)
 template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er, T ch)
+__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er)
 {
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -195,18 +212,18 @@ __device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er, T c
             if (ck.hZone & (1u << i)) {
                 const T dE = er - ck.E[i];
                 ck.pH[i] = fmat(ck.aH[i], dE, ck.bH[i] * ck.pH[i]);
-                ck.H[i] = fmat(-ch, dE + ck.pH[i], ck.H[i]);
+                ck.H[i] = fmat(ck.nch, dE + ck.pH[i], ck.H[i]);
                 continue;
             }
         }
-        ck.H[i] = h_update<T>(ck.H[i], ck.E[i], er, ch);
+        ck.H[i] = fmat(ck.nch, er - ck.E[i], ck.H[i]);
     }
 }
 
 // E^{n+1} (before the source) of the chunk; Hl = H of the node before the
 // chunk.
 template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T ce)
+__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl)
 {
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -219,9 +236,9 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl, T c
         }
         if constexpr (PLASMA) {
             // the plasma formula reproduces the vacuum update at vacuum nodes
-            ck.E[i] = e_update_plasma(ck.E[i], ck.J[i], curl, ck.cf[i]);
+            ck.E[i] = e_update_plasma_neg(ck.E[i], ck.J[i], curl, ck.cf[i].eJ, ck.cf[i].eH, ck.cf[i].eA);
         } else {
-            ck.E[i] = e_update_vac<T>(ck.E[i], curl, ce);
+            ck.E[i] = fmat(ck.nce, curl, ck.E[i]);   // e_update_vac
         }
     }
 }
@@ -248,8 +265,8 @@ template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename Ge
 __device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
                                                  GetEr get_er, GetHl get_hl)
 {
-    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
+    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]));
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]));
     chunk_j<T, C, PLASMA, CPML>(ck);
 }
 
@@ -348,8 +365,8 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const 
                                            const WaveRole &r, int lane, EndCarry<T> &c, double sv,
                                            GetEr get_er, GetHl get_hl)
 {
-    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]), (T)g.ch);
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]), (T)g.ce);
+    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]));
+    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]));
     uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
     chunk_j<T, C, PLASMA, CPML>(ck);
     const bool mur = g.bc == 0;
