@@ -86,25 +86,43 @@ def roofline(prof, precision):
 
 # Algorithmic floating-point operations per node-update (eqs.(14), (12)+(11)
 # solved, (11)): H: subtract + FMA = 3; vacuum E: 3; plasma E: subtract,
-# multiply, two FMAs = 6; J: multiply + two FMAs = 5.
+# multiply, two FMAs = 6; J: multiply + two FMAs = 5.  At FP32 field precision
+# the J update (eq.(11), with its exp(-nu dt) coefficients) stays in FP64, so
+# a plasma node-update is 9 FP32 and 5 FP64 flops.
 FLOPS_VAC = 6
 FLOPS_PLASMA = 14
-# MI355X vector peak without packed FP32 (disabled in this build): 256 CUs x
-# 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s, FP32 and FP64.
-VALU_PEAK_TFLOPS = 78.6
+FLOPS_PLASMA_FP64_PART = 5
+# MI355X vector peaks from the unit counts: 256 CUs x 2.4 GHz x 2 flops (FMA)
+# x 128 FP32 lanes a CU-cycle = 157.3 TFLOP/s (reached by the two-operand FP32
+# forms without packed math: a wave64 v_fmac_f32 / v_sub_f32 issues every
+# ~2.4 cycles on the box), x 64 FP64 lanes = 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 
 
-def alu_roofline(prof, kernel, steps_per_launch):
+def alu_peak(kernel, precision):
+    """Peak for the kernel's own flop mix: the time the chip needs for its
+    FP32 flops at the FP32 rate plus its FP64 flops at the FP64 rate."""
+    plasma = kernel in ("tiled_plasma", "tiled_cpml", "tiled_role")
+    total = FLOPS_PLASMA if plasma else FLOPS_VAC
+    f64 = total if precision == "f64" else (FLOPS_PLASMA_FP64_PART if plasma else 0)
+    return total / ((total - f64) / FP32_PEAK_TFLOPS + f64 / FP64_PEAK_TFLOPS)
+
+
+def alu_roofline(prof, kernel, steps_per_launch, precision):
     """The tiled kernels do K steps per launch on data held in VGPRs; their
     ceiling is VALU issue: achieved = algorithmic flops of the node-updates a
-    launch delivers / mean launch time."""
+    launch delivers / mean launch time, against the peak of the kernel's
+    FP32/FP64 flop mix."""
     ms_tot, calls, units = prof[kernel]
     per = FLOPS_PLASMA if kernel in ("tiled_plasma", "tiled_cpml", "tiled_role") else FLOPS_VAC
     flops = per * units / calls * steps_per_launch
     avg_s = ms_tot / calls / 1e3
     ach = flops / avg_s / 1e12
-    return {"kernel": kernel, "bound": "alu", "achieved": round(ach, 2), "peak": VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4), "traffic": None,
+    peak = round(alu_peak(kernel, precision), 1)
+    return {"kernel": kernel, "bound": "alu", "achieved": round(ach, 2), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+            "peak_basis": "FP32 157.3 and FP64 78.6 TFLOP/s weighted by the kernel's flop mix",
             "flops_per_launch": int(flops), "avg_launch_us": round(avg_s * 1e6, 2), "launches": calls}
 
 
@@ -445,7 +463,7 @@ def main():
     cells = p.n
     value = cells * T / (ms / 1e3) / 1e6
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    rl = alu_roofline(prof, dom, tune["steps_per_pass"])
+    rl = alu_roofline(prof, dom, tune["steps_per_pass"], args.precision)
     hv = roofline(prof, args.precision)
     rl["traffic"] = hv["traffic"] = counter_traffic(dom, args.precision, tune, cells)
     # single-step algorithmic bytes per cell-update of this workload (half plasma)
@@ -476,7 +494,7 @@ def main():
             continue
         dom2 = max(prof2.items(), key=lambda kv: kv[1][0])[0]
         out[prec] = {"value": round(cells * T / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(ms2, 3),
-                     "roofline": alu_roofline(prof2, dom2, tune2["steps_per_pass"]),
+                     "roofline": alu_roofline(prof2, dom2, tune2["steps_per_pass"], prec),
                      "hbm_view": roofline(prof2, prec),
                      "tile_cells": tune2["tile_cells"], "steps_per_pass": tune2["steps_per_pass"]}
     if not args.no_legs:
