@@ -202,13 +202,11 @@ PAPER_TABLE2_MS = {1024: (33, 279), 5120: (33, 379), 10240: (33, 504), 20480: (3
                    40960: (53, 1231), 51200: (61, 1467), 61440: (64, 1701)}
 
 
-def table2_leg(precision="f64", reps=5, serial_cells=10240):
+def table2_leg(precision="f64", reps=5):
     """The paper's timing experiment on this GPU: 1000 steps of its slab setup
     at each cell count of its Table 2 (FP64: the paper states no precision),
-    launch shape from the tuner; beside it the paper's GTX 1080 times and, for
-    one size, the serial oracle on this host (the paper's serial column)."""
+    launch shape from the tuner; beside it the paper's GTX 1080 times."""
     import torch
-    import oracle
     from paper_1709_00821_amd import workloads as W
     from paper_1709_00821_amd import tune as TU
     from paper_1709_00821_amd.plasma import FdtdPlasma
@@ -233,17 +231,22 @@ def table2_leg(precision="f64", reps=5, serial_cells=10240):
                      "paper_gtx1080_ms": gpu_ms, "paper_gtx1080_mcells": round(n * T / gpu_ms / 1e3, 1),
                      "vs_paper_gpu": round(gpu_ms / ms, 1)})
         log(f"bench: table-2 size {n}: {ms:.3f} ms (paper GPU {gpu_ms} ms)")
-    p = W.paper_preset(steps=T, n=serial_cells)
-    t0 = time.perf_counter()
-    oracle.run(p, T)
-    ser = (time.perf_counter() - t0) * 1e3
-    gpu = next(r["ms"] for r in rows if r["cells"] == serial_cells)
     return {"context": "paper Table 2 setup, 1000 steps; paper numbers are its own hardware's, not targets",
-            "precision": precision, "rows": rows,
-            "serial_oracle_ms_at": {"cells": serial_cells, "ms": round(ser, 1), "cores": 1,
-                                    "speedup_gpu_vs_serial": round(ser / gpu, 1),
-                                    "paper_speedup_gpu_vs_serial": round(PAPER_TABLE2_MS[serial_cells][1] /
-                                                                         PAPER_TABLE2_MS[serial_cells][0], 2)}}
+            "precision": precision, "rows": rows}
+
+
+def table2_serial(cpu, leg):
+    """The serial oracle's time for one Table 2 size (measured in the CPU
+    baseline leg) beside this GPU's, as the paper sets its serial column beside
+    its GPU's."""
+    s = cpu.get("paper_table2_serial")
+    if not s:
+        return None
+    gpu = next((r["ms"] for r in leg["rows"] if r["cells"] == s["cells"]), None)
+    if gpu is None:
+        return None
+    return {"cells": s["cells"], "ms": s["ms"], "cores": 1, "speedup_gpu_vs_serial": round(s["ms"] / gpu, 1),
+            "paper_speedup_gpu_vs_serial": round(PAPER_TABLE2_MS[s["cells"]][1] / PAPER_TABLE2_MS[s["cells"]][0], 2)}
 
 
 def c1_leg(reps=5):
@@ -364,16 +367,25 @@ def counter_traffic(kernel, precision, tune, cells):
     return None if k is None else int(k["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(p, steps):
+def cpu_baseline(p, steps, table2_cells=10240):
+    """The serial FP64 oracle on this host: a bounded sample of the headline
+    workload, plus one size of the paper's Table 2 setup (1000 steps), the
+    paper's serial column."""
     import oracle
+    from paper_1709_00821_amd import workloads as W
     log(f"bench: cpu baseline: oracle on the full {p.n}-cell grid for {steps} steps")
     t0 = time.perf_counter()
     oracle.run(p, steps)
     dt = time.perf_counter() - t0
+    q = W.paper_preset(steps=1000, n=table2_cells)
+    t1 = time.perf_counter()
+    oracle.run(q, 1000)
+    ser = (time.perf_counter() - t1) * 1e3
     return {"value": round(p.n * steps / dt / 1e6, 2), "unit": "Mcell-updates/s", "cores": 1,
             "kind": "oracle",
             "sample": f"full {p.n}-cell grid, {steps} steps (of {p.steps}), serial FP64, "
-                      f"{dt:.1f} s incl. coefficient build"}
+                      f"{dt:.1f} s incl. coefficient build",
+            "paper_table2_serial": {"cells": table2_cells, "steps": 1000, "ms": round(ser, 1)}}
 
 
 def vacuum_spectra(p, precision, T, tune):
@@ -385,17 +397,19 @@ def vacuum_spectra(p, precision, T, tune):
         return h.spectra()[0]
 
 
-def oracle_spectra_lightcone(p, T):
-    """Exact oracle spectra of the full grid: outside the source's light cone
-    the fields stay exactly zero for T steps, so a trimmed grid suffices."""
-    import oracle
-    from paper_1709_00821_amd import workloads as W
-    lo, hi = W.light_cone(p, T)
-    wp2 = p.wp2[lo:hi].copy()
-    wp2[0] = wp2[-1] = 0.0
-    q = p.copy(n=hi - lo, wp2=wp2, nu=p.nu[lo:hi].copy(), src_cell=p.src_cell - lo,
-               probes=p.probes - lo, bc="pec", cpml_cells=0)
-    return oracle.run(q, T)["X"]
+def stored_oracle_spectra(p, T):
+    """The FP64 oracle's spectra of this workload (plasma run, plasma-free
+    run), as written by tests/golden/make_oracle_spectra.py; None when the
+    stored run is another size."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_oracle_spectra as G
+    try:
+        d, Xo, Xvo = G.load()
+    except (OSError, ValueError, KeyError):
+        return None
+    if d["cells"] != p.n or d["steps"] != T or not np.array_equal(np.array(d["freqs_hz"]), p.freqs):
+        return None
+    return Xo, Xvo
 
 
 def main():
@@ -505,12 +519,9 @@ def main():
         out["c1_latency"] = c1_leg()
         out["c3_3d"] = c3_leg()
         out["paper_table2"] = table2_leg()
-    if not args.no_check:
-        log("bench: oracle spectra on the source's light cone (exact), plasma and vacuum runs")
-        t0 = time.perf_counter()
-        Xo = oracle_spectra_lightcone(p, T)
-        Xvo = oracle_spectra_lightcone(p.vacuum(), T)
-        osec = time.perf_counter() - t0
+    stored = None if args.no_check else stored_oracle_spectra(p, T)
+    if stored is not None:
+        Xo, Xvo = stored
         Ro, To = (Xo[0] - Xvo[0]) / Xvo[0], Xo[1] / Xvo[1]
         acc, rerr, terr = {}, {}, {}
         for prec, r in results.items():
@@ -525,9 +536,13 @@ def main():
             terr[prec + "_f_ge_12ghz"] = float(np.max(np.abs(np.abs(Tt[hi]) - np.abs(To[hi]))))
         out["accuracy"] = {"spectra_rel_err_vs_fp64_oracle": acc, "max_abs_R_err": rerr, "max_abs_T_err": terr,
                            "frequencies_ghz": [round(float(p.freqs[0]) / 1e9, 3), round(float(p.freqs[-1]) / 1e9, 3)],
-                           "oracle_seconds": round(osec, 1)}
+                           "oracle": "stored FP64 oracle spectra (tests/golden/c2_oracle_spectra.json)"}
+    elif not args.no_check:
+        out["accuracy"] = {"skipped": "stored oracle spectra cover 2^24 cells x 20000 steps only"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+        if "paper_table2" in out:
+            out["paper_table2"]["serial_oracle_ms_at"] = table2_serial(out["cpu_baseline"], out["paper_table2"])
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,22 @@
+"""The stored oracle spectra that bench.py reads for its accuracy figures are
+the oracle's own output: regenerating them reproduces the file exactly."""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_oracle_spectra as G  # noqa: E402
+
+
+def test_stored_c2_spectra_are_the_oracles():
+    d, Xo, Xvo = G.load()
+    assert (d["cells"], d["steps"]) == (G.CELLS, G.STEPS)
+    new = G.compute()
+    assert new["freqs_hz"] == d["freqs_hz"]
+    for name, X in (("plasma", Xo), ("vacuum", Xvo)):
+        Y = np.array(new[name]["re"]) + 1j * np.array(new[name]["im"])
+        assert np.array_equal(X, Y), name
+    # the plasma-free run transmits the pulse: a nonzero spectrum at both probes
+    assert np.all(np.abs(Xvo) > 0)
