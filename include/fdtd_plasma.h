@@ -43,7 +43,7 @@ enum {
     FDTD_E_UNSUPPORTED = -7   /* valid physics this build does not implement on the GPU */
 };
 
-enum { FDTD_F64 = 0, FDTD_F32 = 1 };
+enum { FDTD_F64 = 0, FDTD_F32 = 1, FDTD_F32_DELTA = 2 };
 
 /* Ends of every grid.  MUR1: first-order Mur at nodes 0 and n-1.  CPML: a
  * convolutional PML of cpml_cells nodes at each end (kappa = 1, alpha = 0,
@@ -77,7 +77,15 @@ enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RE
 typedef struct {
     uint32_t struct_size;        /* sizeof(fdtd_plasma_desc) */
     int32_t precision;           /* FDTD_F64 | FDTD_F32: E, H storage and curl arithmetic (J and
-                                    its eq.(11) update are FP64 at either precision) */
+                                    its eq.(11) update are FP64 at either precision).
+                                    FDTD_F32_DELTA: an accuracy ablation of FDTD_F32 in which the
+                                    eq.(11) update is FP32 arithmetic too, J is rounded to FP32
+                                    every step, and every coefficient is an FP32 number in delta
+                                    form (CA-1, exp(-nu dt)-1, b1, b2 each rounded once from its
+                                    FP64 value); J values stay in the FP64 arrays (each one an FP32
+                                    number), the DFT stays FP64.  Per-step executor only
+                                    (FDTD_EXEC_STEP, or FDTD_EXEC_AUTO, which then takes it); no
+                                    FDTD_FLAG_CHECKPOINT.  Other exec modes return FDTD_E_INVALID. */
     int32_t scheme;              /* FDTD_SCHEME_* */
     int32_t bc;                  /* FDTD_BC_* */
     int32_t exec;                /* FDTD_EXEC_* */

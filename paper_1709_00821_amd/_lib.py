@@ -20,7 +20,7 @@ HEADER3 = os.path.join(os.path.dirname(HERE), "include", "fdtd_plasma3d.h")
 # status codes and enums (include/fdtd_plasma.h)
 OK, E_INVALID, E_UNSTABLE, E_WORKSPACE, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
-F64, F32 = 0, 1
+F64, F32, F32_DELTA = 0, 1, 2
 BC = {"mur": 0, "cpml": 1, "pec": 2}
 EXEC = {"auto": 0, "step": 1, "tiled": 2, "resident": 3, "mixed": 4}
 FLAG_CHECKPOINT = 0x1

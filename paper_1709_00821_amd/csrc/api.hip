@@ -163,6 +163,7 @@ struct fdtd_plasma {
         g.P = P;
         g.SB = SB;
         g.scheme = d.scheme;
+        g.jdelta = d.precision == FDTD_F32_DELTA;
         g.bc = d.bc;
         g.cpmlP = d.bc == FDTD_BC_CPML ? d.cpml_cells : 0;
         g.dt = d.dt;
@@ -202,8 +203,11 @@ int validate(const fdtd_plasma_desc *d)
     if (d->struct_size != sizeof(fdtd_plasma_desc))
         return fail(FDTD_E_INVALID, "struct_size %u != %zu (header/library mismatch)",
                     d->struct_size, sizeof(fdtd_plasma_desc));
-    if (d->precision != FDTD_F64 && d->precision != FDTD_F32)
+    if (d->precision != FDTD_F64 && d->precision != FDTD_F32 && d->precision != FDTD_F32_DELTA)
         return fail(FDTD_E_INVALID, "precision %d", d->precision);
+    if (d->precision == FDTD_F32_DELTA &&
+        ((d->exec != FDTD_EXEC_STEP && d->exec != FDTD_EXEC_AUTO) || (d->flags & FDTD_FLAG_CHECKPOINT)))
+        return fail(FDTD_E_INVALID, "FDTD_F32_DELTA runs on the per-step executor only, without checkpoints");
     if (d->scheme < 0 || d->scheme > 2) return fail(FDTD_E_INVALID, "scheme %d", d->scheme);
     if (d->bc < 0 || d->bc > 2) return fail(FDTD_E_INVALID, "bc %d", d->bc);
     if (d->exec < 0 || d->exec > 4) return fail(FDTD_E_INVALID, "exec %d", d->exec);
@@ -431,7 +435,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     // a single short grid and for batches of short grids alike (no per-step
     // barriers, no idle waves), and the bins beside tiles (MIXED) lose on the
     // 4096-slab batch; RESIDENT and MIXED stay available on request
-    if (p.exec == FDTD_EXEC_AUTO) p.exec = FDTD_EXEC_TILED;
+    if (p.exec == FDTD_EXEC_AUTO) p.exec = d->precision == FDTD_F32_DELTA ? FDTD_EXEC_STEP : FDTD_EXEC_TILED;
     if (p.exec == FDTD_EXEC_RESIDENT) {
         if (!build_bins(d, p))
             return fail(FDTD_E_INVALID, "a grid exceeds %lld nodes, the resident limit", (long long)res_max);

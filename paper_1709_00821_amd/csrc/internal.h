@@ -21,6 +21,7 @@ struct Grids {
     int P;                  // probes per grid
     int SB;                 // sample window length
     int scheme;
+    int jdelta;             // FP32 ablation: eq.(11) in FP32 with FP32 delta-form coefficients
     int bc;                 // FDTD_BC_*
     int cpmlP;              // CPML nodes per end (bc = CPML)
     double dt, dz;

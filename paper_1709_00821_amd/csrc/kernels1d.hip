@@ -112,7 +112,16 @@ __device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, in
     if (k == g.src[b])
         En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
     if (write) {
-        s.J[nxt][off + k] = (wp2 != 0.0) ? j_update<T>(s.J[cur][off + k], (double)Eo, (double)En, c) : 0.0;
+        double Jn = 0.0;
+        if (wp2 != 0.0) {
+            if constexpr (sizeof(T) == 4) {
+                Jn = g.jdelta ? (double)j_update_delta((float)s.J[cur][off + k], Eo, En, c.a, c.b1, c.b2)
+                              : j_update<T>(s.J[cur][off + k], (double)Eo, (double)En, c);
+            } else {
+                Jn = j_update<T>(s.J[cur][off + k], (double)Eo, (double)En, c);
+            }
+        }
+        s.J[nxt][off + k] = Jn;
     }
     return En;
 }

@@ -245,6 +245,15 @@ __device__ __forceinline__ float e_update_plasma_neg(float E, double J, float cu
     return fmat(nH, curl, fmat(nJ, (float)J, fmat(eA, E, E)));
 }
 
+// The FP32 ablation of eq.(11): J_new = J + (a-1) J + b1 E_old + b2 E_new in
+// FP32 arithmetic, every coefficient rounded once to FP32 from its FP64 value
+// (a-1 formed in FP64 first, so exp(-nu dt) keeps its digits near 1).
+__device__ __forceinline__ float j_update_delta(float J, float Eold, float Enew, double a, double b1,
+                                                double b2)
+{
+    return fmat((float)b2, Enew, fmat((float)b1, Eold, fmat((float)(a - 1.0), J, J)));
+}
+
 // J_new = a J + b1 E_old + b2 E_new in FP64 for both field precisions: J is
 // held in FP64 (eq.(11): the exp(-nu dt) fractions and the current they
 // accumulate keep their FP64 accuracy); the E values enter already widened.

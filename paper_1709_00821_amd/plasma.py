@@ -44,7 +44,7 @@ def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: 
     cells, wp2, nu, src, probes, freqs = keep
     d = L.Desc()
     d.struct_size = ctypes.sizeof(L.Desc)
-    d.precision = {"f64": L.F64, "f32": L.F32}[precision]
+    d.precision = {"f64": L.F64, "f32": L.F32, "f32d": L.F32_DELTA}[precision]
     d.scheme = p0.scheme
     d.bc = L.BC[p0.bc]
     d.exec = L.EXEC[exec]

@@ -206,3 +206,18 @@ def test_3d_null_handle(L):
     lib = L.lib()
     assert lib.fdtd3d_step(None, 1) == -1
     assert lib.fdtd3d_destroy(None) == 0
+
+
+def test_fp32_delta_ablation_is_per_step_only(L):
+    """FDTD_F32_DELTA (FP32 eq.(11) ablation) plans on the per-step executor
+    (chosen by auto) and is refused on the others and with checkpoints."""
+    p = W.slab_c1()
+    for ex in ("auto", "step"):
+        d, keep = _desc(p, precision="f32d", exec=ex)
+        assert _code(d)[0] == 0, ex
+    for ex in ("tiled", "resident", "mixed"):
+        d, keep = _desc(p, precision="f32d", exec=ex)
+        assert _code(d)[0] == -1, ex
+        assert b"FDTD_F32_DELTA" in L.lib().fdtd_plasma_last_error()
+    d, keep = _desc(p, precision="f32d", checkpoint=64)
+    assert _code(d)[0] == -1
