@@ -412,6 +412,35 @@ def stored_oracle_spectra(p, T):
     return Xo, Xvo
 
 
+def c1_precision_errors():
+    """|R|, |T| errors of each precision mode on the 1000-cell slab against the
+    stored oracle spectra: FP64, FP32 (FP64 eq.(11)) and the FP32 delta-form
+    ablation of eq.(11) (per-step executor)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_oracle_spectra as G
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd.plasma import reflect_transmit
+    p = W.slab_c1()
+    try:
+        d, Xo, Xvo = G.load(G.OUT_C1)
+    except (OSError, ValueError, KeyError):
+        return None
+    if d["cells"] != p.n or d["steps"] != p.steps or not np.array_equal(np.array(d["freqs_hz"]), p.freqs):
+        return None
+    Ro, To = (Xo[0] - Xvo[0]) / Xvo[0], Xo[1] / Xvo[1]
+    hi = p.freqs >= 12e9
+    out = {"workload": "slab_c1 (1000 cells, 4096 steps, Mur ends)"}
+    for prec in ("f64", "f32", "f32d"):
+        R, Tt, s, _ = reflect_transmit(p, p.steps, precision=prec)
+        dR, dT = np.abs(np.abs(R) - np.abs(Ro)), np.abs(np.abs(Tt) - np.abs(To))
+        out[prec] = {"spectra_rel_err": float(np.max(np.abs(s - Xo)) / np.max(np.abs(Xo))),
+                     "max_abs_R_err": float(dR.max()), "max_abs_T_err": float(dT.max()),
+                     "max_abs_R_err_f_ge_12ghz": float(dR[hi].max()),
+                     "max_abs_T_err_f_ge_12ghz": float(dT[hi].max())}
+    out["f32d"]["mode"] = "ablation: eq.(11) in FP32 with FP32 delta-form coefficients, per-step executor"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -539,6 +568,8 @@ def main():
                            "oracle": "stored FP64 oracle spectra (tests/golden/c2_oracle_spectra.json)"}
     elif not args.no_check:
         out["accuracy"] = {"skipped": "stored oracle spectra cover 2^24 cells x 20000 steps only"}
+    if not args.no_check:
+        out["accuracy_c1_precisions"] = c1_precision_errors()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
         if "paper_table2" in out:

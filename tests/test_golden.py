@@ -20,3 +20,12 @@ def test_stored_c2_spectra_are_the_oracles():
         assert np.array_equal(X, Y), name
     # the plasma-free run transmits the pulse: a nonzero spectrum at both probes
     assert np.all(np.abs(Xvo) > 0)
+
+
+def test_stored_c1_spectra_are_the_oracles():
+    d, Xo, Xvo = G.load(G.OUT_C1)
+    new = G.compute_c1()
+    assert (d["cells"], d["steps"], d["freqs_hz"]) == (new["cells"], new["steps"], new["freqs_hz"])
+    for name, X in (("plasma", Xo), ("vacuum", Xvo)):
+        Y = np.array(new[name]["re"]) + 1j * np.array(new[name]["im"])
+        assert np.array_equal(X, Y), name
