@@ -61,8 +61,17 @@ __host__ __device__ inline void phi_funcs(double x, double &a, double &p1, doubl
             1.0 / 24.0,                // 1/4!
             1.0 / 6.0,                 // 1/3!
             1.0 / 2.0};                // 1/2!
-        double s = inv[0];
-        for (int k = 1; k < 17; ++k) s = __builtin_fma(s, -x, inv[k]);
+        // below x = 2^-7 the terms from x^8/10! on fall under 4e-24 of phi2,
+        // so the sum starts at 1/9! (every workload here: x <= 1e-2 only above
+        // nu = 8e10 s^-1)
+        double s;
+        if (x <= 0.0078125) {
+            s = inv[9];
+            for (int k = 10; k < 17; ++k) s = __builtin_fma(s, -x, inv[k]);
+        } else {
+            s = inv[0];
+            for (int k = 1; k < 17; ++k) s = __builtin_fma(s, -x, inv[k]);
+        }
         p2 = s;
         p1 = __builtin_fma(-x, p2, 1.0);
         a = __builtin_fma(-x, p1, 1.0);
@@ -94,14 +103,17 @@ __host__ __device__ inline Coef node_coef(double wp2, double nu, double dt, doub
     c.b1 = kEps0 * wp2 * dt * (p1 - p2);
     c.b2 = kEps0 * wp2 * dt * p2;
     const double D = 1.0 + 0.5 * w * p2;
-    c.CAm1 = 0.0 - 0.5 * w * p1 / D;
-    c.CA = 1.0 - 0.5 * w * p1 / D;
+    const double rD = 1.0 / D;   // one division; the three quotients by D multiply by it
+    c.CAm1 = 0.0 - 0.5 * w * p1 * rD;
+    c.CA = 1.0 - 0.5 * w * p1 * rD;
     if (scheme == 1) {  // eq.(13) as printed
         c.CJ = dt * (1.0 + a) / (2.0 * kEps0);
         c.CH = dt / (kEps0 * dz);
     } else {
-        c.CJ = dt * (1.0 + a) / (2.0 * kEps0 * D);
-        c.CH = dt / (kEps0 * dz * D);
+        c.CJ = dt * (1.0 + a) * (0.5 / kEps0) * rD;
+        // in vacuum rD = 1 exactly, so CH keeps the bits of dt/(eps0 dz) that
+        // the vacuum update uses
+        c.CH = (dt / (kEps0 * dz)) * rD;
     }
     return c;
 }
