@@ -83,9 +83,10 @@ typedef struct {
                                     every step, and every coefficient is an FP32 number in delta
                                     form (CA-1, exp(-nu dt)-1, b1, b2 each rounded once from its
                                     FP64 value); J values stay in the FP64 arrays (each one an FP32
-                                    number), the DFT stays FP64.  Per-step executor only
-                                    (FDTD_EXEC_STEP, or FDTD_EXEC_AUTO, which then takes it); no
-                                    FDTD_FLAG_CHECKPOINT.  Other exec modes return FDTD_E_INVALID. */
+                                    number), the DFT stays FP64.  Per-step executor or one-wave
+                                    register tiles of 256 or 512 nodes (FDTD_EXEC_STEP, _TILED,
+                                    _AUTO); no FDTD_FLAG_CHECKPOINT.  Other exec modes and tile
+                                    shapes return FDTD_E_INVALID. */
     int32_t scheme;              /* FDTD_SCHEME_* */
     int32_t bc;                  /* FDTD_BC_* */
     int32_t exec;                /* FDTD_EXEC_* */

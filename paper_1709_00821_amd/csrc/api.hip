@@ -206,8 +206,11 @@ int validate(const fdtd_plasma_desc *d)
     if (d->precision != FDTD_F64 && d->precision != FDTD_F32 && d->precision != FDTD_F32_DELTA)
         return fail(FDTD_E_INVALID, "precision %d", d->precision);
     if (d->precision == FDTD_F32_DELTA &&
-        ((d->exec != FDTD_EXEC_STEP && d->exec != FDTD_EXEC_AUTO) || (d->flags & FDTD_FLAG_CHECKPOINT)))
-        return fail(FDTD_E_INVALID, "FDTD_F32_DELTA runs on the per-step executor only, without checkpoints");
+        ((d->exec != FDTD_EXEC_STEP && d->exec != FDTD_EXEC_TILED && d->exec != FDTD_EXEC_AUTO) ||
+         (d->flags & FDTD_FLAG_CHECKPOINT) || d->tile_waves > 1 ||
+         (d->tile_cells != 0 && d->tile_cells != 256 && d->tile_cells != 512)))
+        return fail(FDTD_E_INVALID, "FDTD_F32_DELTA runs on the per-step executor or on one-wave register tiles "
+                                    "of 256 or 512 nodes, without checkpoints");
     if (d->scheme < 0 || d->scheme > 2) return fail(FDTD_E_INVALID, "scheme %d", d->scheme);
     if (d->bc < 0 || d->bc > 2) return fail(FDTD_E_INVALID, "bc %d", d->bc);
     if (d->exec < 0 || d->exec > 4) return fail(FDTD_E_INVALID, "exec %d", d->exec);
@@ -435,7 +438,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     // a single short grid and for batches of short grids alike (no per-step
     // barriers, no idle waves), and the bins beside tiles (MIXED) lose on the
     // 4096-slab batch; RESIDENT and MIXED stay available on request
-    if (p.exec == FDTD_EXEC_AUTO) p.exec = d->precision == FDTD_F32_DELTA ? FDTD_EXEC_STEP : FDTD_EXEC_TILED;
+    if (p.exec == FDTD_EXEC_AUTO) p.exec = FDTD_EXEC_TILED;
     if (p.exec == FDTD_EXEC_RESIDENT) {
         if (!build_bins(d, p))
             return fail(FDTD_E_INVALID, "a grid exceeds %lld nodes, the resident limit", (long long)res_max);

@@ -20,7 +20,7 @@
 
 namespace fdtdp {
 
-template <typename T, int C, int KLASS, bool ROLES>
+template <typename T, int C, int KLASS, bool ROLES, bool JF = false>
 __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, const Tile *tiles,
                                                int64_t ntiles, int nsteps, int slot0)
 {
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     const int b = tl.grid;
     const int64_t off = g.off[b], n = g.n[b];
     const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
-    Chunk<T, C, PLASMA, CPML> ck;
+    Chunk<T, C, PLASMA, CPML, JF> ck;
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
     auto er = [](T e0) { return shfl_down1(e0); };
     auto hl = [](T h) { return shfl_up1(h); };
@@ -147,11 +147,36 @@ void launch_tiledw_w(const Grids &g, State<T> &s, int cur, const Tile *tiles, in
     }
 }
 
+// The FP32 delta-form ablation (g.jdelta): the plasma, CPML and role classes
+// with J and eq.(11) in FP32, for 256- and 512-node tiles (the host refuses
+// other shapes for it).
+template <typename T, int C>
+bool launch_tiled_jf(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
+                     int nsteps, int slot0, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 4 && (C == 4 || C == 8)) {
+        const unsigned nb = (unsigned)((ntiles + 3) / 4);
+        if (klass == 1)
+            hipLaunchKernelGGL((k_tiled<T, C, 1, false, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles,
+                               ntiles, nsteps, slot0);
+        else if (klass == 2)
+            hipLaunchKernelGGL((k_tiled<T, C, 2, true, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles,
+                               ntiles, nsteps, slot0);
+        else
+            hipLaunchKernelGGL((k_tiled<T, C, 1, true, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles,
+                               ntiles, nsteps, slot0);
+        return true;
+    }
+    return false;
+}
+
 template <typename T, int C>
 void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
                     int klass, int nsteps, int slot0, hipStream_t st)
 {
     const unsigned nb = (unsigned)((ntiles + 3) / 4);
+    if (g.jdelta && klass != 0 && launch_tiled_jf<T, C>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st))
+        return;
     if (klass == 0)
         hipLaunchKernelGGL((k_tiled<T, C, 0, false>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
                            nsteps, slot0);

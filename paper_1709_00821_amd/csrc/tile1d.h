@@ -15,12 +15,24 @@ namespace fdtdp {
 
 // ------------------------------------------------------------ chunk state
 
-template <typename T, int C, bool PLASMA, bool CPML>
+template <bool JF>
+struct JType {
+    typedef double type;
+};
+template <>
+struct JType<true> {
+    typedef float type;
+};
+
+// JF: the FP32 delta-form ablation of eq.(11) (J and its update in FP32).
+template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
 struct Chunk {
+    typedef typename JType<JF>::type JT;
     T E[C], H[C];
-    double J[PLASMA ? C : 1];      // the current, held in FP64
-    double Ed[PLASMA ? C : 1];     // E^n widened to FP64 (the J update's E_old), kept across steps
+    JT J[PLASMA ? C : 1];          // the current, held in FP64 (FP32 in the ablation)
+    JT Ed[PLASMA ? C : 1];         // E^n (widened to FP64 unless JF): the J update's E_old, kept across steps
     NodeCoef<T> cf[PLASMA ? C : 1];   // eJ and eH held negated (see chunk_load)
+    float jc[JF && PLASMA ? 3 * C : 1];   // JF: a-1, b1, b2 of each node rounded to FP32
     T nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
     uint32_t pmask;                // bit i: node i is plasma
     T pE[CPML ? C : 1], pH[CPML ? C : 1];
@@ -115,8 +127,8 @@ __device__ __forceinline__ T opaque(T x)
 }
 
 // Load the lane's chunk starting at grid node k0 of grid b (buffer `buf`).
-template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
+__device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                            const State<T> &s, int buf, int b, int64_t off,
                                            int64_t n, int64_t k0, int64_t lim)
 {
@@ -126,9 +138,20 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
     load_chunk<T, C>(s.H[buf] + off, k0, lim, ck.H);
     ck.pmask = 0;
     if constexpr (PLASMA) {
-        load_chunk<double, C>(s.J[buf] + off, k0, lim, ck.J);
+        if constexpr (JF) {
+            // the ablation's J values are FP32 numbers held in the FP64 arrays
+            double Jd[C];
+            load_chunk<double, C>(s.J[buf] + off, k0, lim, Jd);
 #pragma unroll
-        for (int i = 0; i < C; ++i) ck.Ed[i] = (double)ck.E[i];
+            for (int i = 0; i < C; ++i) {
+                ck.J[i] = (float)Jd[i];
+                ck.Ed[i] = ck.E[i];
+            }
+        } else {
+            load_chunk<double, C>(s.J[buf] + off, k0, lim, ck.J);
+#pragma unroll
+            for (int i = 0; i < C; ++i) ck.Ed[i] = (double)ck.E[i];
+        }
         double w[C], v[C];
         load_chunk<double, C>(g.wp2 + off, k0, lim, w);
         load_chunk<double, C>(g.nu + off, k0, lim, v);
@@ -138,6 +161,11 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
             ck.cf[i] = node_coef_t<T>(w[i], v[i], g.dt, g.dz, g.scheme);
             ck.cf[i].eJ = opaque<T>(-ck.cf[i].eJ);
             ck.cf[i].eH = opaque<T>(-ck.cf[i].eH);
+            if constexpr (JF) {
+                ck.jc[3 * i] = (float)(ck.cf[i].a - 1.0);
+                ck.jc[3 * i + 1] = (float)ck.cf[i].b1;
+                ck.jc[3 * i + 2] = (float)ck.cf[i].b2;
+            }
         }
     }
     if constexpr (CPML) {
@@ -174,14 +202,21 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML> &ck, const 
     }
 }
 
-template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
+__device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                             const State<T> &s, int buf, int b, int64_t off,
                                             int64_t n, int64_t k0, int64_t lo, int64_t hi)
 {
     store_chunk<T, C>(s.E[buf] + off, k0, lo, hi, ck.E);
     store_chunk<T, C>(s.H[buf] + off, k0, lo, hi < n ? hi : n - 1, ck.H);   // H has n-1 nodes
-    if constexpr (PLASMA) store_chunk<double, C>(s.J[buf] + off, k0, lo, hi, ck.J);
+    if constexpr (PLASMA && JF) {
+        double Jd[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) Jd[i] = (double)ck.J[i];
+        store_chunk<double, C>(s.J[buf] + off, k0, lo, hi, Jd);
+    } else if constexpr (PLASMA) {
+        store_chunk<double, C>(s.J[buf] + off, k0, lo, hi, ck.J);
+    }
     if constexpr (CPML) {
         const int P = g.cpmlP;
 #pragma unroll
@@ -202,8 +237,8 @@ __device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML> &ck,
 
 // H^{n+1/2} of the chunk; Er = E of the next node after the chunk.  (The
 // update of h_update, with the coefficient held negated.)
-template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er)
+template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
+__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML, JF> &ck, T Er)
 {
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -222,8 +257,8 @@ __device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML> &ck, T Er)
 
 // E^{n+1} (before the source) of the chunk; Hl = H of the node before the
 // chunk.
-template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl)
+template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
+__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck, T Hl)
 {
 #pragma unroll
     for (int i = 0; i < C; ++i) {
@@ -247,10 +282,18 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML> &ck, T Hl)
 // kept from the previous step; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.
 // The Mur ends rewrite E after this and leave their copy stale, which is
 // harmless: end nodes carry no plasma (b1 = 0).
-template <typename T, int C, bool PLASMA, bool CPML>
-__device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML> &ck)
+template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
+__device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML, JF> &ck)
 {
-    if constexpr (PLASMA) {
+    if constexpr (PLASMA && JF) {
+        // the ablation: the operations of j_update_delta on the FP32 coefficients
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const float en = ck.E[i];
+            ck.J[i] = fmat(ck.jc[3 * i + 2], en, fmat(ck.jc[3 * i + 1], ck.Ed[i], fmat(ck.jc[3 * i], ck.J[i], ck.J[i])));
+            ck.Ed[i] = en;
+        }
+    } else if constexpr (PLASMA) {
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const double en = (double)ck.E[i];
@@ -261,13 +304,13 @@ __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML> &ck)
 }
 
 // One time step of a chunk that holds no grid end and no source: H, E, J only.
-template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
-__device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl>
+__device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                                  GetEr get_er, GetHl get_hl)
 {
-    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]));
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]));
-    chunk_j<T, C, PLASMA, CPML>(ck);
+    chunk_h<T, C, PLASMA, CPML, JF>(ck, get_er(ck.E[0]));
+    chunk_e<T, C, PLASMA, CPML, JF>(ck, get_hl(ck.H[C - 1]));
+    chunk_j<T, C, PLASMA, CPML, JF>(ck);
 }
 
 // Where a grid's special nodes sit in one wave's span of 64*C nodes: a
@@ -360,15 +403,15 @@ __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, En
 // Every part runs in every such wave, as selects whose lane condition is
 // false where the wave does not hold the node: no branch, so the registers
 // need no merging copies.
-template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl>
-__device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g,
+template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl>
+__device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                            const WaveRole &r, int lane, EndCarry<T> &c, double sv,
                                            GetEr get_er, GetHl get_hl)
 {
-    chunk_h<T, C, PLASMA, CPML>(ck, get_er(ck.E[0]));
-    chunk_e<T, C, PLASMA, CPML>(ck, get_hl(ck.H[C - 1]));
+    chunk_h<T, C, PLASMA, CPML, JF>(ck, get_er(ck.E[0]));
+    chunk_e<T, C, PLASMA, CPML, JF>(ck, get_hl(ck.H[C - 1]));
     uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
-    chunk_j<T, C, PLASMA, CPML>(ck);
+    chunk_j<T, C, PLASMA, CPML, JF>(ck);
     const bool mur = g.bc == 0;
     {
         const T en1 = r.left_reg ? ck.E[2] : ck.E[1];
@@ -460,8 +503,8 @@ __device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_
 // run the wave issues nothing but the probe stores, which it never waits on.
 // (Every cross-lane read here takes a value all lanes computed: a value
 // computed only in some lanes would be stale in the lane that is read.)
-template <typename T, int C, bool PLASMA, bool CPML, typename GetEr, typename GetHl, typename Post>
-__device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Grids &g, const WaveRole &r,
+template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl, typename Post>
+__device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g, const WaveRole &r,
                                          const WaveProbes &wp, int lane, int b, int64_t wave_lo, int64_t plo,
                                          int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
 {
@@ -477,7 +520,7 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML> &ck, const Gr
         }
         auto one = [&](int st) {
             const double sv = (r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
-            chunk_step<T, C, PLASMA, CPML>(ck, g, r, lane, c, sv, er, hl);
+            chunk_step<T, C, PLASMA, CPML, JF>(ck, g, r, lane, c, sv, er, hl);
             post(base + st);
             if (wp.n > 2) {
                 wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);

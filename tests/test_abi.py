@@ -208,16 +208,16 @@ def test_3d_null_handle(L):
     assert lib.fdtd3d_destroy(None) == 0
 
 
-def test_fp32_delta_ablation_is_per_step_only(L):
+def test_fp32_delta_ablation_plans(L):
     """FDTD_F32_DELTA (FP32 eq.(11) ablation) plans on the per-step executor
-    (chosen by auto) and is refused on the others and with checkpoints."""
+    and on one-wave tiles of 256 or 512 nodes; the resident and mixed
+    executors, other tile shapes and checkpoints are refused."""
     p = W.slab_c1()
-    for ex in ("auto", "step"):
-        d, keep = _desc(p, precision="f32d", exec=ex)
-        assert _code(d)[0] == 0, ex
-    for ex in ("tiled", "resident", "mixed"):
-        d, keep = _desc(p, precision="f32d", exec=ex)
-        assert _code(d)[0] == -1, ex
+    for kw in ({"exec": "auto"}, {"exec": "step"}, {"exec": "tiled"}, {"exec": "tiled", "tile_cells": 256}):
+        d, keep = _desc(p, precision="f32d", **kw)
+        assert _code(d)[0] == 0, kw
+    for kw in ({"exec": "resident"}, {"exec": "mixed"}, {"exec": "tiled", "tile_cells": 768},
+               {"exec": "tiled", "tile_waves": 2}, {"checkpoint": 64}):
+        d, keep = _desc(p, precision="f32d", **kw)
+        assert _code(d)[0] == -1, kw
         assert b"FDTD_F32_DELTA" in L.lib().fdtd_plasma_last_error()
-    d, keep = _desc(p, precision="f32d", checkpoint=64)
-    assert _code(d)[0] == -1

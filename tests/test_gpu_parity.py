@@ -143,6 +143,31 @@ def test_c1_fp32_delta_ablation_error_stated(G):
     assert dR.max() < 5e-4 and dT.max() < 5e-4
 
 
+@pytest.mark.parametrize("tile_cells", [256, 512])
+def test_fp32_delta_tiles_match_per_step_bitwise(G, tile_cells):
+    """The FP32 ablation on register tiles (J and eq.(11) in FP32 registers)
+    gives the bits of the per-step ablation kernel, on grids that span many
+    tiles with Mur and CPML ends."""
+    rng = np.random.default_rng(22)
+    probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 511, 1000, 3001)]
+    probs = [q.copy(freqs=probs[0].freqs) for q in probs]
+    T = 700
+    say(f"case fp32-delta step vs tiled tile_cells={tile_cells} grids={[q.n for q in probs]} steps={T}")
+    Xs, Fs = gpu_run(G, probs, T, "f32d", "step")
+    Xt, Ft = gpu_run(G, probs, T, "f32d", "tiled", tile_cells=tile_cells)
+    assert np.array_equal(Xt, Xs)
+    for b in range(len(probs)):
+        for k in ("E", "H", "J"):
+            assert np.array_equal(Ft[b][k], Fs[b][k]), (b, k)
+    cp = W.slab_c1(n=2000, slab=(800, 1100), probes=(300, 1700)).copy(bc="cpml", cpml_cells=32)
+    Xs, Fs = gpu_run(G, cp, 1500, "f32d", "step")
+    Xt, Ft = gpu_run(G, cp, 1500, "f32d", "tiled", tile_cells=tile_cells)
+    assert np.array_equal(Xt, Xs)
+    assert np.any(Fs[0]["J"] != 0)
+    for k in ("E", "H", "J"):
+        assert np.array_equal(Ft[0][k], Fs[0][k]), k
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_exec_modes_bitwise_identical(G, precision):
     rng = np.random.default_rng(21)
