@@ -105,7 +105,7 @@ def alu_peak(kernel, precision):
     FP32 flops at the FP32 rate plus its FP64 flops at the FP64 rate."""
     plasma = kernel in ("tiled_plasma", "tiled_cpml", "tiled_role")
     total = FLOPS_PLASMA if plasma else FLOPS_VAC
-    f64 = total if precision == "f64" else (FLOPS_PLASMA_FP64_PART if plasma else 0)
+    f64 = total if precision == "f64" else (FLOPS_PLASMA_FP64_PART if plasma and precision == "f32" else 0)
     return total / ((total - f64) / FP32_PEAK_TFLOPS + f64 / FP64_PEAK_TFLOPS)
 
 
@@ -454,6 +454,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the FP32 delta-form ablation run (eq.(11) in FP32)")
     ap.add_argument("--no-legs", action="store_true", help="skip the batched, adjoint and C1 legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
@@ -496,8 +498,8 @@ def main():
     log(f"bench: building the {args.cells}-cell workload")
     p = W.large_c2(n=args.cells, steps=T)
     results = {}
-    for prec in ([args.precision] + ([] if args.no_fp64 else
-                                     [x for x in ("f64",) if x != args.precision])):
+    for prec in ([args.precision] + ([] if args.no_fp64 else [x for x in ("f64",) if x != args.precision])
+                 + ([] if args.no_ablation else ["f32d"])):
         tune = TU.pick(prec, p.n, tile_cells=args.tile_cells, steps_per_pass=args.steps_per_pass)
         ms, X, prof = run_precision(p, prec, T, args.steps, args.warmup, tune)
         results[prec] = (ms, X, prof, tune)
@@ -540,6 +542,9 @@ def main():
                      "roofline": alu_roofline(prof2, dom2, tune2["steps_per_pass"], prec),
                      "hbm_view": roofline(prof2, prec),
                      "tile_cells": tune2["tile_cells"], "steps_per_pass": tune2["steps_per_pass"]}
+        if prec == "f32d":
+            out[prec]["mode"] = ("ablation: FP32 fields with eq.(11) and every coefficient in FP32 "
+                                 "(delta form), not the specified FP32 mode")
     if not args.no_legs:
         out["batched"] = batched_leg()
         out["batched"]["vs_plain"] = round(out["batched"]["value"] / out["value"], 3)

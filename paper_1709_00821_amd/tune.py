@@ -27,6 +27,8 @@ def _bucket(n: int, batched: bool = False) -> str:
 
 def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0,
          batched: bool = False) -> dict:
+    if precision == "f32d":    # the FP32 ablation runs the FP32 tile shapes
+        precision = "f32"
     out = dict(DEFAULT)
     if os.path.exists(CACHE):
         try:
