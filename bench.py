@@ -437,7 +437,7 @@ def c1_precision_errors():
                      "max_abs_R_err": float(dR.max()), "max_abs_T_err": float(dT.max()),
                      "max_abs_R_err_f_ge_12ghz": float(dR[hi].max()),
                      "max_abs_T_err_f_ge_12ghz": float(dT[hi].max())}
-    out["f32d"]["mode"] = "ablation: eq.(11) in FP32 with FP32 delta-form coefficients, per-step executor"
+    out["f32d"]["mode"] = "ablation: eq.(11) in FP32 with FP32 delta-form coefficients"
     return out
 
 

@@ -116,7 +116,7 @@ def test_c1_fp32_error_stated(G):
 def test_c1_fp32_delta_ablation_error_stated(G):
     """The FP32 ablation of eq.(11) (FP32 J arithmetic, every coefficient an
     FP32 number in delta form): its |R|, |T| error against the FP64 oracle,
-    stated beside the FP32 mode's, on the per-step executor."""
+    stated beside the FP32 mode's (register tiles, the executor auto picks)."""
     p = W.slab_c1()
     T = p.steps
     say(f"case c1 two-run R/T fp32-delta ablation steps={T}")
