@@ -149,7 +149,8 @@ def test_fp32_delta_tiles_match_per_step_bitwise(G, tile_cells):
     gives the bits of the per-step ablation kernel, on grids that span many
     tiles with Mur and CPML ends."""
     rng = np.random.default_rng(22)
-    probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 511, 1000, 3001)]
+    # 257 and 513 put node n-1 on the first node of a wave (shifted tiles)
+    probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 257, 511, 513, 1000, 3001)]
     probs = [q.copy(freqs=probs[0].freqs) for q in probs]
     T = 700
     say(f"case fp32-delta step vs tiled tile_cells={tile_cells} grids={[q.n for q in probs]} steps={T}")
