@@ -83,7 +83,7 @@ struct AdjView {
     const T *lE, *lH, *lJ;      // lambda^{m+1}
     T *nE, *nH, *nJ;            // lambda^m
     const T *En;                // forward E^m
-    const double *Jn;           // forward J^m (FP64)
+    const double *Jn;           // forward P^{m-1} = J^m - b2 E^m (FP64)
     const T *Hh, *En1;          // forward H^{m+1/2}, E^{m+1}
 };
 
@@ -140,7 +140,8 @@ __global__ void k_adj_step(Grids g, AdjView<T> v, const double *tab, int64_t tot
         const double dCA = tab[6 * total + off + k], dCJ = tab[7 * total + off + k];
         const double dCH = tab[8 * total + off + k], dB1 = tab[9 * total + off + k];
         const double dB2 = tab[10 * total + off + k];
-        const double e0 = (double)v.En[off + k], j0 = (double)v.Jn[off + k];
+        // the stored forward state carries P^{m-1} = J^m - b2 E^m
+        const double e0 = (double)v.En[off + k], j0 = __builtin_fma(B2[off + k], e0, v.Jn[off + k]);
         const double curl = (double)v.Hh[off + k] - (double)v.Hh[off + k - 1];
         const double e1 = (double)v.En1[off + k];
         grad[off + k] += es * (dCA * e0 - dCJ * j0 - dCH * curl) + lj * (dB1 * e0 + dB2 * e1);
@@ -407,8 +408,9 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
             double nE = CA[i] * es[i] + B1[i] * lj + ch * (lHn[i] - lhm);
             const double curl = (double)hh[i] - (double)((i > 0) ? hh[i - 1] : hhp);
             const double e0d = (double)e0[i], e1d = (double)e1[i];
+            const double jm = __builtin_fma(B2[i], e0d, j0[i]);   // J^m from the stored P^{m-1}
             const double gnew =
-                gr[i] + (es[i] * (dCA[i] * e0d - dCJ[i] * j0[i] - dCH[i] * curl) + lj * (dB1[i] * e0d + dB2[i] * e1d));
+                gr[i] + (es[i] * (dCA[i] * e0d - dCJ[i] * jm - dCH[i] * curl) + lj * (dB1[i] * e0d + dB2[i] * e1d));
             if constexpr (ROLE) {
                 const int k = (int)(k0 + i);
                 nE = (mur && k == 1) ? nE + lEp0 : nE;

@@ -1014,6 +1014,16 @@ int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, d
     if ((rc = fetch(h->d_E[h->cur], E, n, h->esize))) return rc;
     if ((rc = fetch(h->d_H[h->cur], H, n - 1, h->esize))) return rc;
     if ((rc = fetch(h->d_J[h->cur], J, n, 8))) return rc;
+    if (J && h->d.precision != FDTD_F32_DELTA) {
+        // the state carries P^{n-1} = J^n - b2 E^n: J^n = P + b2 E^n, with b2 of
+        // eq.(11) from the node's wp2 and nu
+        std::vector<double> En(n), w(n), v(n);
+        if ((rc = fetch(h->d_E[h->cur], En.data(), n, h->esize))) return rc;
+        if ((rc = fetch(h->d_wp2, w.data(), n, 8))) return rc;
+        if ((rc = fetch(h->d_nu, v.data(), n, 8))) return rc;
+        for (int64_t k = 0; k < n; ++k)
+            if (w[k] != 0.0) J[k] = std::fma(node_coef(w[k], v[k], h->d.dt, h->d.dz, h->d.scheme).b2, En[k], J[k]);
+    }
     return FDTD_OK;
 }
 

@@ -101,27 +101,29 @@ __device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, in
     }
     const T Eo = s.E[cur][off + k];
     const double wp2 = g.wp2[off + k];
+    // the J arrays hold P^{n-1} = J^n - b2 E^n (the FP32 ablation: J^n itself)
+    const double Po = s.J[cur][off + k];
     T En;
     NodeCoef<T> c;
     if (wp2 != 0.0) {
         c = node_coef_t<T>(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
-        En = e_update_plasma(Eo, s.J[cur][off + k], curl, c);
+        En = g.jdelta ? e_update_plasma(Eo, Po, curl, c) : e_update_plasma_p(Eo, Po, curl, c);
     } else {
         En = e_update_vac<T>(Eo, curl, (T)g.ce);
     }
     if (k == g.src[b])
         En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
     if (write) {
-        double Jn = 0.0;
+        double Pn = 0.0;
         if (wp2 != 0.0) {
             if constexpr (sizeof(T) == 4) {
-                Jn = g.jdelta ? (double)j_update_delta((float)s.J[cur][off + k], Eo, En, c.a, c.b1, c.b2)
-                              : j_update<T>(s.J[cur][off + k], (double)Eo, (double)En, c);
+                Pn = g.jdelta ? (double)j_update_delta((float)Po, Eo, En, c.a, c.b1, c.b2)
+                              : p_update<T>(Po, (double)Eo, c);
             } else {
-                Jn = j_update<T>(s.J[cur][off + k], (double)Eo, (double)En, c);
+                Pn = p_update<T>(Po, (double)Eo, c);
             }
         }
-        s.J[nxt][off + k] = Jn;
+        s.J[nxt][off + k] = Pn;
     }
     return En;
 }

@@ -29,8 +29,8 @@ template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
 struct Chunk {
     typedef typename JType<JF>::type JT;
     T E[C], H[C];
-    JT J[PLASMA ? C : 1];          // the current, held in FP64 (FP32 in the ablation)
-    JT Ed[PLASMA ? C : 1];         // E^n (widened to FP64 unless JF): the J update's E_old, kept across steps
+    JT J[PLASMA ? C : 1];          // P = J - b2 E in FP64 (the ablation: J itself, in FP32)
+    JT Ed[JF && PLASMA ? C : 1];   // the ablation: E^n, the J update's E_old, kept across steps
     NodeCoef<T> cf[PLASMA ? C : 1];   // eJ and eH held negated (see chunk_load)
     float jc[JF && PLASMA ? 3 * C : 1];   // JF: a-1, b1, b2 of each node rounded to FP32
     T nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
@@ -149,8 +149,6 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
             }
         } else {
             load_chunk<double, C>(s.J[buf] + off, k0, lim, ck.J);
-#pragma unroll
-            for (int i = 0; i < C; ++i) ck.Ed[i] = (double)ck.E[i];
         }
         double w[C], v[C];
         load_chunk<double, C>(g.wp2 + off, k0, lim, w);
@@ -269,19 +267,26 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck, T Hl)
                 curl = curl + ck.pE[i];
             }
         }
-        if constexpr (PLASMA) {
-            // the plasma formula reproduces the vacuum update at vacuum nodes
+        if constexpr (PLASMA && JF) {
             ck.E[i] = e_update_plasma_neg(ck.E[i], ck.J[i], curl, ck.cf[i].eJ, ck.cf[i].eH, ck.cf[i].eA);
+        } else if constexpr (PLASMA) {
+            // P^n from E^n before E^n is overwritten, then E^{n+1} from P^{n-1}
+            // (e_update_plasma_p, p_update); the plasma formula reproduces the
+            // vacuum update at vacuum nodes
+            const double pn = p_update<T>(ck.J[i], (double)ck.E[i], ck.cf[i]);
+            ck.E[i] = e_update_plasma_neg(ck.E[i], ck.J[i], curl, ck.cf[i].eJ, ck.cf[i].eH, ck.cf[i].eP);
+            ck.J[i] = pn;
         } else {
             ck.E[i] = fmat(ck.nce, curl, ck.E[i]);   // e_update_vac
         }
     }
 }
 
-// J update of the chunk (after the source), with E_old the FP64 copy of E^n
-// kept from the previous step; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.
-// The Mur ends rewrite E after this and leave their copy stale, which is
-// harmless: end nodes carry no plasma (b1 = 0).
+// The ablation's J update (after the source), with E_old the copy of E^n kept
+// from the previous step; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.  The
+// Mur ends rewrite E after this and leave their copy stale, which is harmless:
+// end nodes carry no plasma (b1 = 0).  (The carried P is advanced inside
+// chunk_e.)
 template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
 __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML, JF> &ck)
 {
@@ -291,13 +296,6 @@ __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML, JF> &ck)
         for (int i = 0; i < C; ++i) {
             const float en = ck.E[i];
             ck.J[i] = fmat(ck.jc[3 * i + 2], en, fmat(ck.jc[3 * i + 1], ck.Ed[i], fmat(ck.jc[3 * i], ck.J[i], ck.J[i])));
-            ck.Ed[i] = en;
-        }
-    } else if constexpr (PLASMA) {
-#pragma unroll
-        for (int i = 0; i < C; ++i) {
-            const double en = (double)ck.E[i];
-            ck.J[i] = j_update<T>(ck.J[i], ck.Ed[i], en, ck.cf[i]);
             ck.Ed[i] = en;
         }
     }

@@ -39,7 +39,14 @@ def test_fp64_adjoint_matches_oracle(G, bc, T):
     Lo, go, Xo = oracle.adjoint_r2(p, T, xv)
     with G.FdtdPlasma(p, precision="f64", exec="tiled", checkpoint=T) as h:
         L, g = h.grad_r2(T, xv.reshape(1, -1))
-    assert abs(L[0] - Lo) <= 1e-12 * abs(Lo)
+    # L = sum |R|^2 with R = (X - Xv)/Xv (two-run reflection): the spectra's
+    # relative bound 1e-12, amplified by the condition number of that
+    # difference, 2 max |X| / |X - Xv| (about 2e4 for the short run, whose
+    # reflected part is still small)
+    Xr = Xo[0] if np.ndim(Xo) > 1 else Xo
+    cond = 2.0 * float(np.max(np.abs(Xr) / np.abs(Xr - xv)))
+    say(f"loss rel. error {abs(L[0] - Lo) / abs(Lo):.2e}, condition {cond:.1e}")
+    assert abs(L[0] - Lo) <= 1e-12 * max(1.0, cond) * abs(Lo)
     assert np.max(np.abs(g - go)) <= 1e-10 * np.max(np.abs(go))
 
 
