@@ -243,7 +243,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             ck.E[i] = ck.H[i] = (T)0;
-            ck.J[i] = ck.Ed[i] = 0.0;
+            ck.J[i] = 0.0;
         }
         ck.pmask = 0;
     }

@@ -292,9 +292,9 @@ __device__ __forceinline__ float j_update_delta(float J, float Eold, float Enew,
     return fmat((float)b2, Enew, fmat((float)b1, Eold, fmat((float)(a - 1.0), J, J)));
 }
 
-// J_new = a J + b1 E_old + b2 E_new in FP64 for both field precisions: J is
-// held in FP64 (eq.(11): the exp(-nu dt) fractions and the current they
-// accumulate keep their FP64 accuracy); the E values enter already widened.
+// J_new = a J + b1 E_old + b2 E_new in FP64 for both field precisions (the 3D
+// steps; the 1D steps carry P instead, see NodeCoef): eq.(11)'s exp(-nu dt)
+// fractions keep their FP64 accuracy; the E values enter already widened.
 template <typename T>
 __device__ __forceinline__ double j_update(double J, double Eold, double Enew, const NodeCoef<T> &c)
 {
