@@ -99,6 +99,7 @@ struct fdtd_plasma {
     double *d_adj_srcv = nullptr;  // source values of the segment being recomputed
     int64_t ntiles[kTileClasses] = {0, 0, 0, 0};
     int64_t tile_first[kTileClasses] = {0, 0, 0, 0};
+    int64_t group_n[kTileClasses][kRoleGroups] = {};
     int tileC = 8, Kh = 16, tileW = 1;
 
     // resident executor
@@ -295,6 +296,7 @@ struct Plan {
     std::vector<int64_t> off;
     std::vector<Tile> tiles;
     int64_t ntiles[kTileClasses] = {0, 0, 0, 0}, tile_first[kTileClasses] = {0, 0, 0, 0};
+    int64_t group_n[kTileClasses][kRoleGroups] = {};   // tiles of each role group, in group order within a class
     std::vector<ResidentSlot> slots;
     int64_t nbins = 0;
     int exec = 0, tileC = 8, Kh = 16, tileW = 1, resC = 8, resWaves = 8;
@@ -348,6 +350,14 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
     for (int k = 0; k < kTileClasses; ++k) {
         p.tile_first[k] = (int64_t)p.tiles.size();
         p.ntiles[k] = (int64_t)cls[k].size();
+        for (int r = 0; r < kRoleGroups; ++r) p.group_n[k][r] = 0;
+        if (k >= 2 && p.tileW == 1 && p.ntiles[k] >= kRoleGroupMinTiles) {
+            std::stable_sort(cls[k].begin(), cls[k].end(),
+                             [](const Tile &a, const Tile &b) { return role_group(a.flags) < role_group(b.flags); });
+            for (const Tile &t : cls[k]) ++p.group_n[k][role_group(t.flags)];
+        } else {
+            p.group_n[k][kRoleGroups - 1] = p.ntiles[k];
+        }
         p.tiles.insert(p.tiles.end(), cls[k].begin(), cls[k].end());
     }
 }
@@ -565,6 +575,20 @@ void prof_end(fdtd_plasma *h)
     (void)hipEventRecord(h->marks.back().b, h->stream);
 }
 
+// One pass of tile class c: one launch, or, for a CPML or role class sorted
+// into role groups, one launch per group.
+template <typename T>
+void launch_class(fdtd_plasma *h, const Grids &g, State<T> &s, int cur, int c, int nsteps, int slot,
+                  hipStream_t st)
+{
+    int64_t first = h->tile_first[c];
+    for (int r = 0; r < kRoleGroups; ++r) {
+        const int64_t n = h->group_n[c][r];
+        if (n) launch_tiled<T>(g, s, cur, h->d_tiles + first, n, c, h->tileC, nsteps, slot, st, h->tileW, r);
+        first += n;
+    }
+}
+
 // Fold the full sample window into X.
 void flush(fdtd_plasma *h)
 {
@@ -621,17 +645,13 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
             if (fork) {
                 (void)hipEventRecord(h->ev_fork, h->stream);
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-                for (int c = 2; c < kTileClasses; ++c)
-                    if (h->ntiles[c])
-                        launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC,
-                                        (int)k, slot, h->side, h->tileW);
+                for (int c = 2; c < kTileClasses; ++c) launch_class<T>(h, g, s, h->cur, c, (int)k, slot, h->side);
                 (void)hipEventRecord(h->ev_join, h->side);
             }
             for (int c = 0; c < kTileClasses; ++c)
                 if (h->ntiles[c] && !on_side(c)) {
                     prof_begin(h, kTiledNames[c], h->class_nodes[c]);
-                    launch_tiled<T>(g, s, h->cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c,
-                                    h->tileC, (int)k, slot, h->stream, h->tileW);
+                    launch_class<T>(h, g, s, h->cur, c, (int)k, slot, h->stream);
                     prof_end(h);
                 }
             if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
@@ -659,8 +679,7 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                 for (int c = 0; c < kTileClasses; ++c)
                     if (h->ntiles[c]) {
                         prof_begin(h, kTiledNames[c], h->class_nodes[c]);
-                        launch_tiled<T>(g, s, cur, h->d_tiles + h->tile_first[c], h->ntiles[c], c, h->tileC, kk,
-                                        slot + (int)done, h->stream, h->tileW);
+                        launch_class<T>(h, g, s, cur, c, kk, slot + (int)done, h->stream);
                         prof_end(h);
                     }
                 cur ^= 1;
@@ -748,6 +767,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     for (int k = 0; k < kTileClasses; ++k) {
         h->ntiles[k] = p.ntiles[k];
         h->tile_first[k] = p.tile_first[k];
+        for (int r = 0; r < kRoleGroups; ++r) h->group_n[k][r] = p.group_n[k][r];
         for (int64_t t = 0; t < p.ntiles[k]; ++t) {
             const Tile &tl = p.tiles[p.tile_first[k] + t];
             h->class_nodes[k] += tl.out_hi - tl.out_lo;

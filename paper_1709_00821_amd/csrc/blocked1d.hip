@@ -20,7 +20,7 @@
 
 namespace fdtdp {
 
-template <typename T, int C, int KLASS, bool ROLES, bool JF = false>
+template <typename T, int C, int KLASS, bool ROLES, bool JF = false, int RM = kRoleAll>
 __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, const Tile *tiles,
                                                int64_t ntiles, int nsteps, int slot0)
 {
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
         WaveProbes wp;
         wp.n = 0;
         if (tl.flags & TILE_PROBE) wp = wave_probes_find<C>(g, b, tl.lo, tl.out_lo, tl.out_hi);
-        run_role<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0, er,
-                                     hl, [](int) {});
+        run_role<T, C, PLASMA, CPML, RM>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0,
+                                         er, hl, [](int) {});
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
@@ -170,9 +170,43 @@ bool launch_tiled_jf(const Grids &g, State<T> &s, int cur, const Tile *tiles, in
     return false;
 }
 
+template <typename T, int C, int KLASS, int RM>
+void launch_roles(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int nsteps,
+                  int slot0, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((ntiles + 3) / 4);
+    hipLaunchKernelGGL((k_tiled<T, C, KLASS, true, false, RM>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles,
+                       ntiles, nsteps, slot0);
+}
+
+// A role group's tiles with the step compiled for its roles (256- and
+// 512-node tiles; wider tiles take the full step).
+template <typename T, int C, int KLASS>
+void launch_group(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int group,
+                  int nsteps, int slot0, hipStream_t st)
+{
+    if constexpr (C == 4 || C == 8) {
+        switch (group) {
+        case 0: return launch_roles<T, C, KLASS, kRoleProbe>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+        case 1:
+            return launch_roles<T, C, KLASS, kRoleSrc | kRoleProbe>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+        case 2:
+            return launch_roles<T, C, KLASS, kRoleLeft | kRoleProbe>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+        case 3:
+            return launch_roles<T, C, KLASS, kRoleRight | kRoleProbe>(g, s, cur, tiles, ntiles, nsteps, slot0,
+                                                                     st);
+        case 4:
+            return launch_roles<T, C, KLASS, kRoleLeft | kRoleSrc | kRoleProbe>(g, s, cur, tiles, ntiles, nsteps,
+                                                                               slot0, st);
+        default: break;
+        }
+    }
+    launch_roles<T, C, KLASS, kRoleAll>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+}
+
 template <typename T, int C>
 void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
-                    int klass, int nsteps, int slot0, hipStream_t st)
+                    int klass, int nsteps, int slot0, hipStream_t st, int group)
 {
     const unsigned nb = (unsigned)((ntiles + 3) / 4);
     if (g.jdelta && klass != 0 && launch_tiled_jf<T, C>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st))
@@ -184,32 +218,30 @@ void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int
         hipLaunchKernelGGL((k_tiled<T, C, 1, false>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
                            nsteps, slot0);
     else if (klass == 2)
-        hipLaunchKernelGGL((k_tiled<T, C, 2, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
-                           nsteps, slot0);
+        launch_group<T, C, 2>(g, s, cur, tiles, ntiles, group, nsteps, slot0, st);
     else   // role tiles, vacuum or plasma: the plasma step reproduces the vacuum one
-        hipLaunchKernelGGL((k_tiled<T, C, 1, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
-                           nsteps, slot0);
+        launch_group<T, C, 1>(g, s, cur, tiles, ntiles, group, nsteps, slot0, st);
 }
 
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
-                  int C, int nsteps, int slot0, hipStream_t st, int waves)
+                  int C, int nsteps, int slot0, hipStream_t st, int waves, int group)
 {
     if (waves == 2) return launch_tiledw_w<T, 2>(g, s, cur, tiles, ntiles, klass, C, nsteps, slot0, st);
     if (waves == 4) return launch_tiledw_w<T, 4>(g, s, cur, tiles, ntiles, klass, C, nsteps, slot0, st);
     if (waves == 8) return launch_tiledw_w<T, 8>(g, s, cur, tiles, ntiles, klass, C, nsteps, slot0, st);
     switch (C) {
-    case 4: launch_tiled_c<T, 4>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
-    case 8: launch_tiled_c<T, 8>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
-    case 12: launch_tiled_c<T, 12>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
-    default: launch_tiled_c<T, 16>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st); break;
+    case 4: launch_tiled_c<T, 4>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
+    case 8: launch_tiled_c<T, 8>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
+    case 12: launch_tiled_c<T, 12>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
+    default: launch_tiled_c<T, 16>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
     }
 }
 
 template void launch_tiled<float>(const Grids &, State<float> &, int, const Tile *, int64_t, int, int,
-                                  int, int, hipStream_t, int);
+                                  int, int, hipStream_t, int, int);
 template void launch_tiled<double>(const Grids &, State<double> &, int, const Tile *, int64_t, int,
-                                   int, int, int, hipStream_t, int);
+                                   int, int, int, hipStream_t, int, int);
 
 // ------------------------------------------------------------- resident
 

@@ -84,6 +84,32 @@ constexpr int kTwiddleChunk = 1024;
 // other tiles holding a grid end, the source or a probe.
 constexpr int kTileClasses = 4;
 
+// Roles a one-wave tile may hold, as bits of a mask.  A CPML or role class
+// with at least kRoleGroupMinTiles tiles is sorted into role groups and each
+// group is launched with the role step compiled for its mask (a tile holding
+// only the right end then runs no source or left-end code); smaller classes,
+// whose launches are latency bound, take one launch with the full step.  The
+// probe part, and the source part, still check at run time whether the tile
+// has one.
+enum : int { kRoleSrc = 1, kRoleLeft = 2, kRoleRight = 4, kRoleProbe = 8, kRoleAll = 15 };
+constexpr int kRoleGroups = 6;
+constexpr int64_t kRoleGroupMinTiles = 2048;
+// group of a tile from its TILE_* flags: probe only, source, left end, right
+// end, left end and source, anything else
+inline int role_group(int flags)
+{
+    const int m = ((flags & TILE_SOURCE) ? kRoleSrc : 0) | ((flags & TILE_LEFT_END) ? kRoleLeft : 0) |
+                  ((flags & TILE_RIGHT_END) ? kRoleRight : 0);
+    switch (m) {
+    case 0: return 0;
+    case kRoleSrc: return 1;
+    case kRoleLeft: return 2;
+    case kRoleRight: return 3;
+    case kRoleLeft | kRoleSrc: return 4;
+    default: return 5;
+    }
+}
+
 // ---- kernel launchers (kernels1d.hip) ------------------------------------
 template <typename T>
 void launch_step(const Grids &g, State<T> &s, int cur, int64_t total_nodes, int64_t m,
@@ -91,9 +117,12 @@ void launch_step(const Grids &g, State<T> &s, int cur, int64_t total_nodes, int6
 
 // Tiles of `waves` waves (1: one wave a tile, neighbours by DPP only; 2, 4,
 // 8: one workgroup a tile, neighbouring waves through LDS).
+// group: the role group of every tile of a CPML or role-class launch of
+// one-wave tiles (kRoleGroups - 1: the full role step).
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
-                  int klass, int C, int nsteps, int slot0, hipStream_t st, int waves = 1);
+                  int klass, int C, int nsteps, int slot0, hipStream_t st, int waves = 1,
+                  int group = kRoleGroups - 1);
 
 // Forward recompute of nsteps steps from segment slot slot0, every step's
 // state stored (tiles of kTraceCells nodes with a kTraceHalo halo, nsteps <=

@@ -398,20 +398,22 @@ __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, En
 // One full time step of a wave holding a grid end, the source or a probe: H,
 // E, the source (added to E^{n+1}, eq.(15), before the J update), J, then the
 // ends (first-order Mur, or PEC E = 0).  sv: the source value of this step.
+// Only the parts of the roles in mask RM are compiled in.
 // Every part runs in every such wave, as selects whose lane condition is
 // false where the wave does not hold the node: no branch, so the registers
 // need no merging copies.
-template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl>
+template <typename T, int C, bool PLASMA, bool CPML, int RM, bool JF, typename GetEr, typename GetHl>
 __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                            const WaveRole &r, int lane, EndCarry<T> &c, double sv,
                                            GetEr get_er, GetHl get_hl)
 {
     chunk_h<T, C, PLASMA, CPML, JF>(ck, get_er(ck.E[0]));
     chunk_e<T, C, PLASMA, CPML, JF>(ck, get_hl(ck.H[C - 1]));
-    uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
+    if constexpr ((RM & kRoleSrc) != 0)
+        uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
     chunk_j<T, C, PLASMA, CPML, JF>(ck);
     const bool mur = g.bc == 0;
-    {
+    if constexpr ((RM & kRoleLeft) != 0) {
         const T en1 = r.left_reg ? ck.E[2] : ck.E[1];
         const T v = mur ? (T)(c.e1 + (T)g.cm * (en1 - c.e0)) : (T)0;
         const bool here = lane == r.left_lane;
@@ -420,7 +422,7 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, co
         c.e0 = v;
         c.e1 = en1;
     }
-    {
+    if constexpr ((RM & kRoleRight) != 0) {
         const int ir = r.right_reg;
         const T prev = shfl_up1(ck.E[C - 1]);
         const T left1 = upick<T, C>(ck.E, ir > 0 ? ir - 1 : 0);
@@ -501,26 +503,29 @@ __device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_
 // run the wave issues nothing but the probe stores, which it never waits on.
 // (Every cross-lane read here takes a value all lanes computed: a value
 // computed only in some lanes would be stale in the lane that is read.)
-template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl, typename Post>
+template <typename T, int C, bool PLASMA, bool CPML, int RM = kRoleAll, bool JF = false, typename GetEr,
+          typename GetHl, typename Post>
 __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g, const WaveRole &r,
                                          const WaveProbes &wp, int lane, int b, int64_t wave_lo, int64_t plo,
                                          int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
 {
+    constexpr bool SRC = (RM & kRoleSrc) != 0;
     EndCarry<T> c;
     ends_init<T, C>(ck.E, r, c);
     for (int base = 0; base < nsteps; base += 64) {
         const int cnt = nsteps - base < 64 ? nsteps - base : 64;
         const int slot = slot0 + base;
         double svl = 0.0;
-        if (r.src_lane >= 0) {
+        if (SRC && r.src_lane >= 0) {
             const int i = slot + lane;
             svl = g.srcv[i < g.SB ? i : g.SB - 1];
         }
         auto one = [&](int st) {
-            const double sv = (r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
-            chunk_step<T, C, PLASMA, CPML, JF>(ck, g, r, lane, c, sv, er, hl);
+            const double sv = (SRC && r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
+            chunk_step<T, C, PLASMA, CPML, RM>(ck, g, r, lane, c, sv, er, hl);
             post(base + st);
-            if (wp.n > 2) {
+            if constexpr ((RM & kRoleProbe) == 0) {
+            } else if (wp.n > 2) {
                 wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
             } else {
                 if (wp.n > 0) wave_probe_store<T, C>(g, wp.lane[0], wp.reg[0], wp.row[0], lane, ck.E, slot + st);

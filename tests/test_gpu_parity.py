@@ -170,6 +170,25 @@ def test_fp32_delta_tiles_match_per_step_bitwise(G, tile_cells):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_role_groups_bitwise(G, precision):
+    """A batch with more role tiles than the grouping threshold (2048): the
+    role tiles are launched per role group (probe only, source, left end,
+    right end, left end with source, other) with the step compiled for each,
+    and give the bits of the per-step path."""
+    rng = np.random.default_rng(23)
+    probs = [W.random_slab(rng, int(n), n_freqs=4) for n in rng.integers(600, 1500, 1100)]
+    probs = [q.copy(freqs=probs[0].freqs) for q in probs]
+    T = 200
+    say(f"case role groups {precision} slabs={len(probs)} steps={T}")
+    Xs, Fs = gpu_run(G, probs, T, precision, "step")
+    Xt, Ft = gpu_run(G, probs, T, precision, "tiled", tile_cells=512, steps_per_pass=48)
+    assert np.array_equal(Xt, Xs)
+    for b in range(0, len(probs), 37):
+        for k in ("E", "H", "J"):
+            assert np.array_equal(Ft[b][k], Fs[b][k]), (b, k)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_exec_modes_bitwise_identical(G, precision):
     rng = np.random.default_rng(21)
     probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 511, 512, 513, 1000, 2049, 3001)]
