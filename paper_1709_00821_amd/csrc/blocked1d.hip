@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     // class 0: vacuum tiles; 1: tiles with plasma; 2: tiles touching a CPML
     // layer (which may also hold plasma further in).  ROLES: the tiles hold a
     // grid end, the source or a probe (a separate instantiation, so that the
-    // bulk tiles' register budget is that of the plain step alone)
+    // bulk tiles' register budget is that of the plain step alone), at most
+    // the roles of mask RM.  JF: the FP32 ablation of eq.(11)
     constexpr bool PLASMA = KLASS >= 1;
     constexpr bool CPML = KLASS == 2;
     const int lane = threadIdx.x & 63;

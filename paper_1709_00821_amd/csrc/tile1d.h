@@ -301,7 +301,8 @@ __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML, JF> &ck)
     }
 }
 
-// One time step of a chunk that holds no grid end and no source: H, E, J only.
+// One time step of a chunk that holds no grid end and no source: H, then E
+// with the carried P (or, in the ablation, E then J).
 template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl>
 __device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                                  GetEr get_er, GetHl get_hl)
@@ -395,10 +396,11 @@ __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, En
     c.eR1 = ir ? upick<T, C>(E, ir - 1) : shfl_up1(E[C - 1]);
 }
 
-// One full time step of a wave holding a grid end, the source or a probe: H,
-// E, the source (added to E^{n+1}, eq.(15), before the J update), J, then the
-// ends (first-order Mur, or PEC E = 0).  sv: the source value of this step.
-// Only the parts of the roles in mask RM are compiled in.
+// One full time step of a wave holding a grid end, the source or a probe: H;
+// E with the carried P (the P update reads E^n first); the source, added to
+// E^{n+1} (eq.(15)); the ablation's J update; then the ends (first-order Mur,
+// or PEC E = 0).  sv: the source value of this step.  Only the parts of the
+// roles in mask RM are compiled in.
 // Every part runs in every such wave, as selects whose lane condition is
 // false where the wave does not hold the node: no branch, so the registers
 // need no merging copies.
