@@ -582,9 +582,14 @@ void launch_class(fdtd_plasma *h, const Grids &g, State<T> &s, int cur, int c, i
                   hipStream_t st)
 {
     int64_t first = h->tile_first[c];
+    // an unsplit CPML or role class (below the grouping threshold): one launch
+    // whose waves each take the role code of their own group
+    const bool mixed = c >= 2 && h->tileW == 1 && h->group_n[c][kRoleGroups - 1] == h->ntiles[c];
     for (int r = 0; r < kRoleGroups; ++r) {
         const int64_t n = h->group_n[c][r];
-        if (n) launch_tiled<T>(g, s, cur, h->d_tiles + first, n, c, h->tileC, nsteps, slot, st, h->tileW, r);
+        if (n)
+            launch_tiled<T>(g, s, cur, h->d_tiles + first, n, c, h->tileC, nsteps, slot, st, h->tileW,
+                            mixed ? -1 : r);
         first += n;
     }
 }

@@ -57,8 +57,12 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
         WaveProbes wp;
         wp.n = 0;
         if (tl.flags & TILE_PROBE) wp = wave_probes_find<C>(g, b, tl.lo, tl.out_lo, tl.out_hi);
-        run_role<T, C, PLASMA, CPML, RM>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0,
-                                         er, hl, [](int) {});
+        if constexpr (RM < 0)   // a small mixed class: each wave picks its role code
+            run_role_any<T, C, PLASMA, CPML>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0,
+                                             er, hl, [](int) {});
+        else
+            run_role<T, C, PLASMA, CPML, RM>(ck, g, role, wp, lane, b, tl.lo, tl.out_lo, tl.out_hi, nsteps, slot0,
+                                             er, hl, [](int) {});
     }
     chunk_store<T, C, PLASMA, CPML>(ck, g, s, cur ^ 1, b, off, n, k0, tl.out_lo, tl.out_hi);
 }
@@ -199,6 +203,7 @@ void launch_group(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64
         case 4:
             return launch_roles<T, C, KLASS, kRoleLeft | kRoleSrc | kRoleProbe>(g, s, cur, tiles, ntiles, nsteps,
                                                                                slot0, st);
+        case -1: return launch_roles<T, C, KLASS, -1>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
         default: break;
         }
     }

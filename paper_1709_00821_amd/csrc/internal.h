@@ -118,7 +118,8 @@ void launch_step(const Grids &g, State<T> &s, int cur, int64_t total_nodes, int6
 // Tiles of `waves` waves (1: one wave a tile, neighbours by DPP only; 2, 4,
 // 8: one workgroup a tile, neighbouring waves through LDS).
 // group: the role group of every tile of a CPML or role-class launch of
-// one-wave tiles (kRoleGroups - 1: the full role step).
+// one-wave tiles (kRoleGroups - 1: the full role step; -1: a small mixed
+// class, each wave picking the code of its own group).
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles,
                   int klass, int C, int nsteps, int slot0, hipStream_t st, int waves = 1,

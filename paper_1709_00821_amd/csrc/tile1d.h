@@ -543,6 +543,31 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
     }
 }
 
+// run_role for a wave of a small mixed role class: the wave takes the code
+// compiled for the first role group covering its roles (the groups of
+// role_group), chosen at run time.  Used where a class is too small to be
+// split into per-group launches (its launch is latency bound, so the
+// registers the several instantiations hold do not cost occupancy).
+template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl, typename Post>
+__device__ __forceinline__ void run_role_any(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g, const WaveRole &r,
+                                             const WaveProbes &wp, int lane, int b, int64_t wave_lo, int64_t plo,
+                                             int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
+{
+    const int rm = (r.src_lane >= 0 ? kRoleSrc : 0) | (r.left_lane >= 0 ? kRoleLeft : 0) |
+                   (r.right_lane >= 0 ? kRoleRight : 0);
+#define FDTDP_ROLE(M) \
+    run_role<T, C, PLASMA, CPML, M>(ck, g, r, wp, lane, b, wave_lo, plo, phi, nsteps, slot0, er, hl, post)
+    switch (rm) {
+    case 0: FDTDP_ROLE(kRoleProbe); break;
+    case kRoleSrc: FDTDP_ROLE(kRoleSrc | kRoleProbe); break;
+    case kRoleLeft: FDTDP_ROLE(kRoleLeft | kRoleProbe); break;
+    case kRoleRight: FDTDP_ROLE(kRoleRight | kRoleProbe); break;
+    case kRoleLeft | kRoleSrc: FDTDP_ROLE(kRoleLeft | kRoleSrc | kRoleProbe); break;
+    default: FDTDP_ROLE(kRoleAll); break;
+    }
+#undef FDTDP_ROLE
+}
+
 // Block index remapped so that each XCD (workgroups are dealt round-robin to
 // the 8 XCDs) receives a contiguous range of tiles and neighbouring tiles
 // share an L2.
