@@ -56,7 +56,12 @@ enum { FDTD_BC_MUR1 = 0, FDTD_BC_CPML = 1, FDTD_BC_PEC = 2 };
  * the E^n term carries 1/D).  ETD1: the first-order current update eq.(9). */
 enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 = 2 };
 
-/* How the time loop is executed (results agree bit for bit across modes):
+/* How the time loop is executed.  In FDTD_F64 and FDTD_F32_DELTA the results
+ * agree bit for bit across modes.  In FDTD_F32 the fields are held in FP64
+ * registers while a launch runs and rounded to FP32 where it stores them, so
+ * the bits depend on where launches end (STEP: every step; TILED: every
+ * steps_per_pass steps and at window ends; RESIDENT: every sample window), and
+ * each mode agrees with the FP64 result to its own rounding level.
  * STEP:     two launches per time step (H, then E/J/source/ends/probes);
  * TILED:    temporal blocking, steps_per_pass steps per launch on register
  *           tiles of tile_waves waves of tile_cells nodes each, with halo
@@ -67,7 +72,10 @@ enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 
  *           the longer ones as TILED tiles (Mur or PEC ends; batches of
  *           uneven slabs);
  * AUTO:     TILED (faster than RESIDENT on MI355X for single grids and for
- *           batches of short grids alike). */
+ *           batches of short grids alike), except RESIDENT for FDTD_F32 on at
+ *           most 16 grids that all fit the resident bins (4095 nodes) with Mur
+ *           or PEC ends: fewer FP32 roundings keep short runs within the FP32
+ *           accuracy target at the low end of the band. */
 enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RESIDENT = 3,
        FDTD_EXEC_MIXED = 4 };
 
@@ -76,23 +84,27 @@ enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RE
 
 typedef struct {
     uint32_t struct_size;        /* sizeof(fdtd_plasma_desc) */
-    int32_t precision;           /* FDTD_F64 | FDTD_F32: E, H storage and curl arithmetic (J and
-                                    its eq.(11) update are FP64 at either precision).
-                                    FDTD_F32_DELTA: an accuracy ablation of FDTD_F32 in which the
-                                    eq.(11) update is FP32 arithmetic too, J is rounded to FP32
-                                    every step, and every coefficient is an FP32 number in delta
-                                    form (CA-1, exp(-nu dt)-1, b1, b2 each rounded once from its
-                                    FP64 value); J values stay in the FP64 arrays (each one an FP32
+    int32_t precision;           /* FDTD_F64: E, H (and psi) stored in FP64.  FDTD_F32: stored in
+                                    FP32, the updates computed in FP64 registers and rounded to
+                                    FP32 only where a launch stores the fields (see the exec
+                                    modes).  J (carried as J - b2 E) and its eq.(11) update are
+                                    FP64 at either precision; the DFT is FP64.
+                                    FDTD_F32_DELTA: an accuracy ablation with every field update in
+                                    FP32 arithmetic (fields rounded to FP32 after every operation),
+                                    the eq.(11) update in FP32 too with J rounded to FP32 every
+                                    step, and every coefficient an FP32 number in delta form
+                                    (CA-1, exp(-nu dt)-1, b1, b2 each rounded once from its FP64
+                                    value); J values stay in the FP64 arrays (each one an FP32
                                     number), the DFT stays FP64.  Per-step executor or one-wave
                                     register tiles of 256 or 512 nodes (FDTD_EXEC_STEP, _TILED,
-                                    _AUTO); no FDTD_FLAG_CHECKPOINT.  Other exec modes and tile
-                                    shapes return FDTD_E_INVALID. */
+                                    _AUTO, which takes TILED); no FDTD_FLAG_CHECKPOINT.  Other exec
+                                    modes and tile shapes return FDTD_E_INVALID. */
     int32_t scheme;              /* FDTD_SCHEME_* */
     int32_t bc;                  /* FDTD_BC_* */
     int32_t exec;                /* FDTD_EXEC_* */
     int32_t flags;               /* FDTD_FLAG_* */
     int64_t batch;               /* number of independent 1D grids, >= 1 */
-    const int64_t *cells;        /* host [batch]: E nodes per grid, >= 3 */
+    const int64_t *cells;        /* host [batch]: E nodes per grid, in [3, 2^31 - 1] */
     double dz;                   /* m, > 0 */
     double dt;                   /* s, > 0, c dt/dz <= 1 */
     const double *wp2;           /* host [sum(cells)]: plasma frequency^2 per node, rad^2/s^2, >= 0;

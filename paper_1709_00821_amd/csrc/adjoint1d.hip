@@ -239,13 +239,14 @@ __global__ __launch_bounds__(256) void k_trace(Grids g, char *seg, int64_t slot_
     s0.H[0] = slotH(slot0);
     s0.J[0] = slotJ(slot0);
     Chunk<T, C, true, false> ck;
+    typedef typename Chunk<T, C, true, false>::R R;
     chunk_load<T, C, true, false>(ck, g, s0, 0, b, off, n, k0, tl.hi);
-    auto er = [](T e0) { return shfl_down1(e0); };
-    auto hl = [](T h) { return shfl_up1(h); };
+    auto er = [](R e0) { return shfl_down1(e0); };
+    auto hl = [](R h) { return shfl_up1(h); };
     auto post = [&](int st) {
         const int i = slot0 + st + 1;
-        store_chunk<T, C>(slotE(i) + off, k0, tl.out_lo, tl.out_hi, ck.E);
-        store_chunk<T, C>(slotH(i) + off, k0, tl.out_lo, tl.out_hi < n ? tl.out_hi : n - 1, ck.H);
+        store_chunk_as<T, C>(slotE(i) + off, k0, tl.out_lo, tl.out_hi, ck.E);
+        store_chunk_as<T, C>(slotH(i) + off, k0, tl.out_lo, tl.out_hi < n ? tl.out_hi : n - 1, ck.H);
         store_chunk<double, C>(slotJ(i) + off, k0, tl.out_lo, tl.out_hi, ck.J);
     };
     const WaveRole role = wave_role<C>(g, b, n, tl.lo, tl.hi);

@@ -235,8 +235,9 @@ int validate(const fdtd_plasma_desc *d)
     int64_t o = 0;
     for (int64_t b = 0; b < d->batch; ++b) {
         const int64_t n = d->cells[b];
-        if (n < 3 || n > (int64_t)1 << 31)
-            return fail(FDTD_E_INVALID, "grid %lld: cells %lld out of [3, 2^31]", (long long)b,
+        // tiles address nodes with 32-bit indices (one past the last node included)
+        if (n < 3 || n > (int64_t)INT32_MAX)
+            return fail(FDTD_E_INVALID, "grid %lld: cells %lld out of [3, 2^31 - 1]", (long long)b,
                         (long long)n);
         if (d->bc == FDTD_BC_CPML && 2 * (int64_t)d->cpml_cells >= n)
             return fail(FDTD_E_INVALID, "grid %lld: CPML of %d nodes per end needs more than %lld nodes",
@@ -447,8 +448,18 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     // AUTO takes the register tiles: on MI355X they beat the resident bins for
     // a single short grid and for batches of short grids alike (no per-step
     // barriers, no idle waves), and the bins beside tiles (MIXED) lose on the
-    // 4096-slab batch; RESIDENT and MIXED stay available on request
-    if (p.exec == FDTD_EXEC_AUTO) p.exec = FDTD_EXEC_TILED;
+    // 4096-slab batch; RESIDENT and MIXED stay available on request.  The
+    // exception is FP32 storage on a few grids that fit the bins: there the
+    // resident executor keeps the fields in FP64 registers for a whole sample
+    // window, so they are rounded to FP32 once a window instead of once a
+    // tile pass, which is what keeps a short run's reflection and
+    // transmission at the low end of the band within the FP32 target.
+    if (p.exec == FDTD_EXEC_AUTO) {
+        p.exec = FDTD_EXEC_TILED;
+        bool fits = d->precision == FDTD_F32 && d->bc != FDTD_BC_CPML && d->batch <= kResidentAutoGrids;
+        for (int64_t b = 0; fits && b < d->batch; ++b) fits = d->cells[b] + 1 <= res_max;
+        if (fits) p.exec = FDTD_EXEC_RESIDENT;
+    }
     if (p.exec == FDTD_EXEC_RESIDENT) {
         if (!build_bins(d, p))
             return fail(FDTD_E_INVALID, "a grid exceeds %lld nodes, the resident limit", (long long)res_max);

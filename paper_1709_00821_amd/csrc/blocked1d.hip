@@ -40,9 +40,10 @@ __global__ __launch_bounds__(256) void k_tiled(Grids g, State<T> s, int cur, con
     const int64_t off = g.off[b], n = g.n[b];
     const int64_t k0 = (int64_t)tl.lo + (int64_t)lane * C;
     Chunk<T, C, PLASMA, CPML, JF> ck;
+    typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
     chunk_load<T, C, PLASMA, CPML>(ck, g, s, cur, b, off, n, k0, tl.hi);
-    auto er = [](T e0) { return shfl_down1(e0); };
-    auto hl = [](T h) { return shfl_up1(h); };
+    auto er = [](R e0) { return shfl_down1(e0); };
+    auto hl = [](R h) { return shfl_up1(h); };
     if constexpr (!ROLES) {
         // two steps per trip: the loop-carried E copies then alternate
         // registers instead of being moved back every step
@@ -80,8 +81,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
 {
     constexpr bool PLASMA = KLASS >= 1;
     constexpr bool CPML = KLASS == 2;
-    __shared__ T ldsE[WAVES];
-    __shared__ T ldsH[WAVES];
+    typedef typename Chunk<T, C, PLASMA, CPML>::R R;
+    __shared__ R ldsE[WAVES];
+    __shared__ R ldsH[WAVES];
     const int lane = threadIdx.x & 63;
     const int w = uniform(threadIdx.x >> 6);
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
@@ -99,18 +101,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_tiledw(Grids g, State<T> s, int 
     // probes this wave samples: tile outputs inside the wave's span
     const int64_t plo = tl.out_lo > wave_lo ? tl.out_lo : wave_lo;
     const int64_t phi = tl.out_hi < wave_hi ? tl.out_hi : wave_hi;
-    auto er = [&](T e0) {
+    auto er = [&](R e0) {
         if (lane == 0) ldsE[w] = e0;
         __syncthreads();
-        T v = shfl_down1(e0);
-        if (lane == 63) v = (w + 1 < WAVES) ? ldsE[w + 1] : (T)0;
+        R v = shfl_down1(e0);
+        if (lane == 63) v = (w + 1 < WAVES) ? ldsE[w + 1] : (R)0;
         return v;
     };
-    auto hl = [&](T h) {
+    auto hl = [&](R h) {
         if (lane == 63) ldsH[w] = h;
         __syncthreads();
-        T v = shfl_up1(h);
-        if (lane == 0) v = (w > 0) ? ldsH[w - 1] : (T)0;
+        R v = shfl_up1(h);
+        if (lane == 0) v = (w > 0) ? ldsH[w - 1] : (R)0;
         return v;
     };
     WaveProbes wp;
@@ -152,16 +154,19 @@ void launch_tiledw_w(const Grids &g, State<T> &s, int cur, const Tile *tiles, in
     }
 }
 
-// The FP32 delta-form ablation (g.jdelta): the plasma, CPML and role classes
-// with J and eq.(11) in FP32, for 256- and 512-node tiles (the host refuses
-// other shapes for it).
+// The FP32 delta-form ablation (g.jdelta): every class with the field
+// updates in FP32 registers and, where there is plasma, J and eq.(11) in
+// FP32, for 256- and 512-node tiles (the host refuses other shapes for it).
 template <typename T, int C>
 bool launch_tiled_jf(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
                      int nsteps, int slot0, hipStream_t st)
 {
     if constexpr (sizeof(T) == 4 && (C == 4 || C == 8)) {
         const unsigned nb = (unsigned)((ntiles + 3) / 4);
-        if (klass == 1)
+        if (klass == 0)
+            hipLaunchKernelGGL((k_tiled<T, C, 0, false, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles,
+                               ntiles, nsteps, slot0);
+        else if (klass == 1)
             hipLaunchKernelGGL((k_tiled<T, C, 1, false, true>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles,
                                ntiles, nsteps, slot0);
         else if (klass == 2)
@@ -215,7 +220,7 @@ void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int
                     int klass, int nsteps, int slot0, hipStream_t st, int group)
 {
     const unsigned nb = (unsigned)((ntiles + 3) / 4);
-    if (g.jdelta && klass != 0 && launch_tiled_jf<T, C>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st))
+    if (g.jdelta && launch_tiled_jf<T, C>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st))
         return;
     if (klass == 0)
         hipLaunchKernelGGL((k_tiled<T, C, 0, false>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles,
@@ -259,8 +264,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
                                                          const ResidentSlot *slots, int nsteps,
                                                          int slot0)
 {
-    __shared__ T ldsE[WAVES];
-    __shared__ T ldsH[WAVES];
+    typedef typename Chunk<T, C, true, false>::R R;
+    __shared__ R ldsE[WAVES];
+    __shared__ R ldsH[WAVES];
     const int lane = threadIdx.x & 63;
     const int w = uniform(threadIdx.x >> 6);
     const ResidentSlot sl = slots[(int64_t)blockIdx.x * WAVES + w];
@@ -280,24 +286,24 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
     else {
 #pragma unroll
         for (int i = 0; i < C; ++i) {
-            ck.E[i] = ck.H[i] = (T)0;
+            ck.E[i] = ck.H[i] = (R)0;
             ck.J[i] = 0.0;
         }
         ck.pmask = 0;
     }
     const WaveRole role = active ? wave_role<C>(g, b, n, wave_lo, wave_hi) : WaveRole{-1, 0, -1, 0, -1, 1};
-    auto get_er = [&](T e0) {
+    auto get_er = [&](R e0) {
         if (lane == 0) ldsE[w] = e0;
         __syncthreads();
-        T v = shfl_down1(e0);
-        if (lane == 63) v = has_next ? ldsE[w + 1] : (T)0;
+        R v = shfl_down1(e0);
+        if (lane == 63) v = has_next ? ldsE[w + 1] : (R)0;
         return v;
     };
-    auto get_hl = [&](T hl) {
+    auto get_hl = [&](R hl) {
         if (lane == 63) ldsH[w] = hl;
         __syncthreads();
-        T v = shfl_up1(hl);
-        if (lane == 0) v = has_prev ? ldsH[w - 1] : (T)0;
+        R v = shfl_up1(hl);
+        if (lane == 0) v = has_prev ? ldsH[w - 1] : (R)0;
         return v;
     };
     const int64_t plo = wave_lo < 0 ? 0 : wave_lo;

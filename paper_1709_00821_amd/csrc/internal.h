@@ -77,6 +77,9 @@ struct ResidentSlot {
     int32_t shift;        // 1: node k sits at position k+1 (keeps n-2, n-1 in one lane)
 };
 
+// AUTO picks the resident executor for FP32 storage on at most this many grids
+// when all of them fit the bins (see plan() in api.hip).
+constexpr int64_t kResidentAutoGrids = 16;
 // Samples folded into the DFT per twiddle table (table: kTwiddleChunk x F).
 constexpr int kTwiddleChunk = 1024;
 // Tile classes of the temporally blocked executor: 0 vacuum, 1 plasma (both

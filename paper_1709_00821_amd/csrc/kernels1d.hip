@@ -47,6 +47,34 @@ __device__ __forceinline__ int cpml_h_slot(int P, int64_t n, int64_t k, int &tab
 
 // ------------------------------------------------------ per-step reference
 
+// Arithmetic of the per-step kernels: R is the register type (FP64, or FP32 in
+// the FP32 ablation); values are read from and rounded to the storage type T
+// every step.
+
+// H^{n+1/2} of node k of grid b (and its psi, written to buffer nxt).
+template <typename T, typename R>
+__device__ __forceinline__ R step_h_val(const Grids &g, const State<T> &s, int cur, int b, int64_t off,
+                                        int64_t n, int64_t k)
+{
+    const int nxt = cur ^ 1;
+    const T *E = s.E[cur] + off;
+    const R El = (R)E[k], Er = (R)E[k + 1];
+    const R Ho = (R)s.H[cur][off + k];
+    if (g.bc == 1) {
+        int tab;
+        const int slot = cpml_h_slot(g.cpmlP, n, k, tab);
+        if (slot >= 0) {
+            const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
+            const R dE = Er - El;
+            const R bH = (R)g.cpml[2 * g.cpmlP + tab], aH = (R)g.cpml[3 * g.cpmlP + tab];
+            const R psi = fmat(aH, dE, bH * (R)s.psiH[cur][ps]);
+            s.psiH[nxt][ps] = (T)psi;
+            return fmat(-(R)g.ch, dE + psi, Ho);
+        }
+    }
+    return h_update<R>(Ho, El, Er, (R)g.ch);
+}
+
 // H^{n+1/2} of every node, written to buffer nxt.
 template <typename T>
 __global__ void k_step_h(Grids g, State<T> s, int cur, int64_t total)
@@ -56,76 +84,79 @@ __global__ void k_step_h(Grids g, State<T> s, int cur, int64_t total)
     const int b = grid_of(g, i);
     const int64_t off = g.off[b], n = g.n[b], k = i - off;
     if (k > n - 2) return;
-    const int nxt = cur ^ 1;
-    const T *E = s.E[cur] + off;
-    const T dE = E[k + 1] - E[k];
     T Hn;
-    if (g.bc == 1) {
-        int tab;
-        const int slot = cpml_h_slot(g.cpmlP, n, k, tab);
-        if (slot >= 0) {
-            const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
-            const T bH = (T)g.cpml[2 * g.cpmlP + tab], aH = (T)g.cpml[3 * g.cpmlP + tab];
-            const T psi = fmat(aH, dE, bH * s.psiH[cur][ps]);
-            s.psiH[nxt][ps] = psi;
-            Hn = fmat(-(T)g.ch, dE + psi, s.H[cur][off + k]);
-        } else {
-            Hn = h_update<T>(s.H[cur][off + k], E[k], E[k + 1], (T)g.ch);
-        }
-    } else {
-        Hn = h_update<T>(s.H[cur][off + k], E[k], E[k + 1], (T)g.ch);
-    }
-    s.H[nxt][off + k] = Hn;
+    if (sizeof(T) == 4 && g.jdelta)
+        Hn = (T)step_h_val<T, float>(g, s, cur, b, off, n, k);
+    else
+        Hn = (T)step_h_val<T, double>(g, s, cur, b, off, n, k);
+    s.H[cur ^ 1][off + k] = Hn;
 }
 
 // E^{n+1} (and J^{n+1}, psiE) of interior node k of grid b; H already at
 // n+1/2 in buffer nxt.  Returns the new E; writes J and psi when asked.
-template <typename T>
-__device__ __forceinline__ T step_interior(const Grids &g, const State<T> &s, int cur, int b,
+template <typename T, typename R>
+__device__ __forceinline__ R step_interior(const Grids &g, const State<T> &s, int cur, int b,
                                            int64_t off, int64_t n, int64_t k, int64_t m,
                                            bool write)
 {
     const int nxt = cur ^ 1;
     const T *H = s.H[nxt] + off;
-    T curl = H[k] - H[k - 1];
+    R curl = (R)H[k] - (R)H[k - 1];
     if (g.bc == 1) {
         int tab;
         const int slot = cpml_e_slot(g.cpmlP, n, k, tab);
         if (slot >= 0) {
             const int64_t ps = (int64_t)b * 2 * g.cpmlP + slot;
-            const T bE = (T)g.cpml[tab], aE = (T)g.cpml[g.cpmlP + tab];
-            const T psi = fmat(aE, curl, bE * s.psiE[cur][ps]);
-            if (write) s.psiE[nxt][ps] = psi;
+            const R bE = (R)g.cpml[tab], aE = (R)g.cpml[g.cpmlP + tab];
+            const R psi = fmat(aE, curl, bE * (R)s.psiE[cur][ps]);
+            if (write) s.psiE[nxt][ps] = (T)psi;
             curl = curl + psi;
         }
     }
-    const T Eo = s.E[cur][off + k];
+    const R Eo = (R)s.E[cur][off + k];
     const double wp2 = g.wp2[off + k];
     // the J arrays hold P^{n-1} = J^n - b2 E^n (the FP32 ablation: J^n itself)
     const double Po = s.J[cur][off + k];
-    T En;
-    NodeCoef<T> c;
+    R En;
+    NodeCoef<R> c;
     if (wp2 != 0.0) {
-        c = node_coef_t<T>(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
+        c = node_coef_t<R>(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
         En = g.jdelta ? e_update_plasma(Eo, Po, curl, c) : e_update_plasma_p(Eo, Po, curl, c);
     } else {
-        En = e_update_vac<T>(Eo, curl, (T)g.ce);
+        En = e_update_vac<R>(Eo, curl, (R)g.ce);
     }
     if (k == g.src[b])
-        En = add_source<T>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
+        En = add_source<R>(En, source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp));
     if (write) {
         double Pn = 0.0;
         if (wp2 != 0.0) {
-            if constexpr (sizeof(T) == 4) {
-                Pn = g.jdelta ? (double)j_update_delta((float)Po, Eo, En, c.a, c.b1, c.b2)
-                              : p_update<T>(Po, (double)Eo, c);
+            if constexpr (sizeof(R) == 4) {
+                Pn = (double)j_update_delta((float)Po, Eo, En, c.a, c.b1, c.b2);
             } else {
-                Pn = p_update<T>(Po, (double)Eo, c);
+                Pn = p_update<R>(Po, (double)Eo, c);
             }
         }
         s.J[nxt][off + k] = Pn;
     }
     return En;
+}
+
+// E^{n+1}, J^{n+1}, ends and probe samples of node k, in registers of type R.
+template <typename T, typename R>
+__device__ __forceinline__ R step_e_val(const Grids &g, const State<T> &s, int cur, int b, int64_t off, int64_t n,
+                                        int64_t k, int64_t m)
+{
+    if (k == 0 || k == n - 1) {
+        s.J[cur ^ 1][off + k] = 0.0;
+        if (g.bc == 0) {  // first-order Mur: E0' = E1 + cm (E1' - E0)
+            const int64_t kn = (k == 0) ? 1 : n - 2;
+            const R Enb = step_interior<T, R>(g, s, cur, b, off, n, kn, m, false);
+            const T *E = s.E[cur] + off;
+            return (R)E[kn] + (R)g.cm * (Enb - (R)E[k]);
+        }
+        return (R)0;
+    }
+    return step_interior<T, R>(g, s, cur, b, off, n, k, m, true);
 }
 
 // E^{n+1}, J^{n+1}, ends and probe samples; reads buffer cur, writes nxt.
@@ -137,22 +168,13 @@ __global__ void k_step_e(Grids g, State<T> s, int cur, int64_t total, int64_t m,
     const int b = grid_of(g, i);
     const int64_t off = g.off[b], n = g.n[b], k = i - off;
     if (k >= n) return;
-    const int nxt = cur ^ 1;
-    T En;
-    if (k == 0 || k == n - 1) {
-        if (g.bc == 0) {  // first-order Mur: E0' = E1 + cm (E1' - E0)
-            const int64_t kn = (k == 0) ? 1 : n - 2;
-            const T Enb = step_interior<T>(g, s, cur, b, off, n, kn, m, false);
-            const T *E = s.E[cur] + off;
-            En = E[kn] + (T)g.cm * (Enb - E[k]);
-        } else {
-            En = (T)0;
-        }
-        s.J[nxt][off + k] = 0.0;
-    } else {
-        En = step_interior<T>(g, s, cur, b, off, n, k, m, true);
-    }
-    s.E[nxt][off + k] = En;
+    double Ed;   // E^{n+1} as the step computed it (before its rounding to T)
+    if (sizeof(T) == 4 && g.jdelta)
+        Ed = (double)step_e_val<T, float>(g, s, cur, b, off, n, k, m);
+    else
+        Ed = step_e_val<T, double>(g, s, cur, b, off, n, k, m);
+    const T En = (T)Ed;
+    s.E[cur ^ 1][off + k] = En;
     for (int p = 0; p < g.P; ++p)
         if (g.probe[(int64_t)b * g.P + p] == k)
             g.samp[((int64_t)b * g.P + p) * g.SB + slot] = (double)En;

@@ -24,19 +24,37 @@ struct JType<true> {
     typedef float type;
 };
 
+// Register type of the field arithmetic for storage type T: FP64, except in
+// the FP32 ablation (JF), whose every update runs in FP32.  FP32 storage with
+// FP64 registers rounds E and H (and psi) to FP32 only where a launch stores
+// them, not after every step: rounding the fields to FP32 after every step
+// lets the rounding errors collect in the modes an open 1D grid does not
+// damp (with first-order Mur ends a uniform offset of E or of H is a steady
+// state), which dominates the reflection and transmission error at the low
+// end of the band.
+template <typename T, bool JF>
+struct RegOf {
+    typedef double type;
+};
+template <>
+struct RegOf<float, true> {
+    typedef float type;
+};
+
 // JF: the FP32 delta-form ablation of eq.(11) (J and its update in FP32).
 template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
 struct Chunk {
     typedef typename JType<JF>::type JT;
-    T E[C], H[C];
+    typedef typename RegOf<T, JF>::type R;
+    R E[C], H[C];
     JT J[PLASMA ? C : 1];          // P = J - b2 E in FP64 (the ablation: J itself, in FP32)
     JT Ed[JF && PLASMA ? C : 1];   // the ablation: E^n, the J update's E_old, kept across steps
-    NodeCoef<T> cf[PLASMA ? C : 1];   // eJ and eH held negated (see chunk_load)
+    NodeCoef<R> cf[PLASMA ? C : 1];   // eJ and eH held negated (see chunk_load)
     float jc[JF && PLASMA ? 3 * C : 1];   // JF: a-1, b1, b2 of each node rounded to FP32
-    T nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
+    R nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
     uint32_t pmask;                // bit i: node i is plasma
-    T pE[CPML ? C : 1], pH[CPML ? C : 1];
-    T bE[CPML ? C : 1], aE[CPML ? C : 1], bH[CPML ? C : 1], aH[CPML ? C : 1];
+    R pE[CPML ? C : 1], pH[CPML ? C : 1];
+    R bE[CPML ? C : 1], aE[CPML ? C : 1], bH[CPML ? C : 1], aH[CPML ? C : 1];
     uint32_t eZone, hZone;         // bit i: node i has an E / H psi
 };
 
@@ -115,6 +133,34 @@ __device__ __forceinline__ void store_chunk(T *a, int64_t k0, int64_t lo, int64_
     }
 }
 
+// load_chunk into registers of type R (widened from the storage type T).
+template <typename T, int C, typename R>
+__device__ __forceinline__ void load_chunk_as(const T *a, int64_t k0, int64_t lim, R (&v)[C])
+{
+    if constexpr (sizeof(T) == sizeof(R)) {
+        load_chunk<T, C>(a, k0, lim, v);
+    } else {
+        T t[C];
+        load_chunk<T, C>(a, k0, lim, t);
+#pragma unroll
+        for (int i = 0; i < C; ++i) v[i] = (R)t[i];
+    }
+}
+
+// store_chunk from registers of type R (each value rounded once to T).
+template <typename T, int C, typename R>
+__device__ __forceinline__ void store_chunk_as(T *a, int64_t k0, int64_t lo, int64_t hi, const R (&v)[C])
+{
+    if constexpr (sizeof(T) == sizeof(R)) {
+        store_chunk<T, C>(a, k0, lo, hi, v);
+    } else {
+        T t[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) t[i] = (T)v[i];
+        store_chunk<T, C>(a, k0, lo, hi, t);
+    }
+}
+
 // x, hidden from the optimiser.  A coefficient negated through here reaches
 // the step's FMAs as a plain register, so they compile to the two-operand
 // accumulate form; a visible negation is folded into the three-operand form
@@ -132,10 +178,11 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
                                            const State<T> &s, int buf, int b, int64_t off,
                                            int64_t n, int64_t k0, int64_t lim)
 {
-    ck.nch = opaque<T>(-(T)g.ch);
-    ck.nce = opaque<T>(-(T)g.ce);
-    load_chunk<T, C>(s.E[buf] + off, k0, lim, ck.E);
-    load_chunk<T, C>(s.H[buf] + off, k0, lim, ck.H);
+    typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
+    ck.nch = opaque<R>(-(R)g.ch);
+    ck.nce = opaque<R>(-(R)g.ce);
+    load_chunk_as<T, C>(s.E[buf] + off, k0, lim, ck.E);
+    load_chunk_as<T, C>(s.H[buf] + off, k0, lim, ck.H);
     ck.pmask = 0;
     if constexpr (PLASMA) {
         if constexpr (JF) {
@@ -156,9 +203,9 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             if (w[i] != 0.0) ck.pmask |= 1u << i;
-            ck.cf[i] = node_coef_t<T>(w[i], v[i], g.dt, g.dz, g.scheme);
-            ck.cf[i].eJ = opaque<T>(-ck.cf[i].eJ);
-            ck.cf[i].eH = opaque<T>(-ck.cf[i].eH);
+            ck.cf[i] = node_coef_t<R>(w[i], v[i], g.dt, g.dz, g.scheme);
+            ck.cf[i].eJ = opaque<R>(-ck.cf[i].eJ);
+            ck.cf[i].eH = opaque<R>(-ck.cf[i].eH);
             if constexpr (JF) {
                 ck.jc[3 * i] = (float)(ck.cf[i].a - 1.0);
                 ck.jc[3 * i + 1] = (float)ck.cf[i].b1;
@@ -172,9 +219,9 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int64_t k = k0 + i;
-            ck.pE[i] = ck.pH[i] = (T)0;
-            ck.bE[i] = ck.bH[i] = (T)1;
-            ck.aE[i] = ck.aH[i] = (T)0;
+            ck.pE[i] = ck.pH[i] = (R)0;
+            ck.bE[i] = ck.bH[i] = (R)1;
+            ck.aE[i] = ck.aH[i] = (R)0;
             if (k < 0 || k >= lim) continue;   // k = -1: a tile shifted off node 0
             int slot = -1, tab = 0;
             // E psi: nodes 1..P-1 and n-P..n-2 (depth d -> table d-1)
@@ -182,9 +229,9 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
             else if (k > n - 1 - P && k <= n - 2) { tab = (int)(k - (n - 1 - P)) - 1; slot = P + (int)(k - (n - P)); }
             if (slot >= 0) {
                 ck.eZone |= 1u << i;
-                ck.pE[i] = s.psiE[buf][(int64_t)b * 2 * P + slot];
-                ck.bE[i] = (T)g.cpml[tab];
-                ck.aE[i] = (T)g.cpml[P + tab];
+                ck.pE[i] = (R)s.psiE[buf][(int64_t)b * 2 * P + slot];
+                ck.bE[i] = (R)g.cpml[tab];
+                ck.aE[i] = (R)g.cpml[P + tab];
             }
             slot = -1;
             // H psi: nodes 0..P-1 and n-1-P..n-2 (depth j+1/2 -> table j)
@@ -192,9 +239,9 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
             else if (k >= n - 1 - P && k <= n - 2) { tab = (int)(k - (n - 1 - P)); slot = P + tab; }
             if (slot >= 0) {
                 ck.hZone |= 1u << i;
-                ck.pH[i] = s.psiH[buf][(int64_t)b * 2 * P + slot];
-                ck.bH[i] = (T)g.cpml[2 * P + tab];
-                ck.aH[i] = (T)g.cpml[3 * P + tab];
+                ck.pH[i] = (R)s.psiH[buf][(int64_t)b * 2 * P + slot];
+                ck.bH[i] = (R)g.cpml[2 * P + tab];
+                ck.aH[i] = (R)g.cpml[3 * P + tab];
             }
         }
     }
@@ -205,8 +252,8 @@ __device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML, JF> 
                                             const State<T> &s, int buf, int b, int64_t off,
                                             int64_t n, int64_t k0, int64_t lo, int64_t hi)
 {
-    store_chunk<T, C>(s.E[buf] + off, k0, lo, hi, ck.E);
-    store_chunk<T, C>(s.H[buf] + off, k0, lo, hi < n ? hi : n - 1, ck.H);   // H has n-1 nodes
+    store_chunk_as<T, C>(s.E[buf] + off, k0, lo, hi, ck.E);
+    store_chunk_as<T, C>(s.H[buf] + off, k0, lo, hi < n ? hi : n - 1, ck.H);   // H has n-1 nodes
     if constexpr (PLASMA && JF) {
         double Jd[C];
 #pragma unroll
@@ -223,11 +270,11 @@ __device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML, JF> 
             if (k < lo || k >= hi) continue;
             if (ck.eZone & (1u << i)) {
                 const int slot = (k < P) ? (int)k : P + (int)(k - (n - P));
-                s.psiE[buf][(int64_t)b * 2 * P + slot] = ck.pE[i];
+                s.psiE[buf][(int64_t)b * 2 * P + slot] = (T)ck.pE[i];
             }
             if (ck.hZone & (1u << i)) {
                 const int slot = (k < P) ? (int)k : P + (int)(k - (n - 1 - P));
-                s.psiH[buf][(int64_t)b * 2 * P + slot] = ck.pH[i];
+                s.psiH[buf][(int64_t)b * 2 * P + slot] = (T)ck.pH[i];
             }
         }
     }
@@ -236,14 +283,16 @@ __device__ __forceinline__ void chunk_store(const Chunk<T, C, PLASMA, CPML, JF> 
 // H^{n+1/2} of the chunk; Er = E of the next node after the chunk.  (The
 // update of h_update, with the coefficient held negated.)
 template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
-__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML, JF> &ck, T Er)
+__device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML, JF> &ck,
+                                        typename Chunk<T, C, PLASMA, CPML, JF>::R Er)
 {
+    typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-        const T er = (i + 1 < C) ? ck.E[i + 1] : Er;
+        const R er = (i + 1 < C) ? ck.E[i + 1] : Er;
         if constexpr (CPML) {
             if (ck.hZone & (1u << i)) {
-                const T dE = er - ck.E[i];
+                const R dE = er - ck.E[i];
                 ck.pH[i] = fmat(ck.aH[i], dE, ck.bH[i] * ck.pH[i]);
                 ck.H[i] = fmat(ck.nch, dE + ck.pH[i], ck.H[i]);
                 continue;
@@ -256,11 +305,13 @@ __device__ __forceinline__ void chunk_h(Chunk<T, C, PLASMA, CPML, JF> &ck, T Er)
 // E^{n+1} (before the source) of the chunk; Hl = H of the node before the
 // chunk.
 template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
-__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck, T Hl)
+__device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck,
+                                        typename Chunk<T, C, PLASMA, CPML, JF>::R Hl)
 {
+    typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-        T curl = ck.H[i] - ((i > 0) ? ck.H[i - 1] : Hl);
+        R curl = ck.H[i] - ((i > 0) ? ck.H[i - 1] : Hl);
         if constexpr (CPML) {
             if (ck.eZone & (1u << i)) {
                 ck.pE[i] = fmat(ck.aE[i], curl, ck.bE[i] * ck.pE[i]);
@@ -273,7 +324,7 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck, T Hl)
             // P^n from E^n before E^n is overwritten, then E^{n+1} from P^{n-1}
             // (e_update_plasma_p, p_update); the plasma formula reproduces the
             // vacuum update at vacuum nodes
-            const double pn = p_update<T>(ck.J[i], (double)ck.E[i], ck.cf[i]);
+            const double pn = p_update<R>(ck.J[i], (double)ck.E[i], ck.cf[i]);
             ck.E[i] = e_update_plasma_neg(ck.E[i], ck.J[i], curl, ck.cf[i].eJ, ck.cf[i].eH, ck.cf[i].eP);
             ck.J[i] = pn;
         } else {
@@ -406,18 +457,20 @@ __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, En
 // need no merging copies.
 template <typename T, int C, bool PLASMA, bool CPML, int RM, bool JF, typename GetEr, typename GetHl>
 __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
-                                           const WaveRole &r, int lane, EndCarry<T> &c, double sv,
+                                           const WaveRole &r, int lane,
+                                           EndCarry<typename Chunk<T, C, PLASMA, CPML, JF>::R> &c, double sv,
                                            GetEr get_er, GetHl get_hl)
 {
+    typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
     chunk_h<T, C, PLASMA, CPML, JF>(ck, get_er(ck.E[0]));
     chunk_e<T, C, PLASMA, CPML, JF>(ck, get_hl(ck.H[C - 1]));
     if constexpr ((RM & kRoleSrc) != 0)
-        uput<T, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<T>(upick<T, C>(ck.E, r.src_reg), sv));
+        uput<R, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<R>(upick<R, C>(ck.E, r.src_reg), sv));
     chunk_j<T, C, PLASMA, CPML, JF>(ck);
     const bool mur = g.bc == 0;
     if constexpr ((RM & kRoleLeft) != 0) {
-        const T en1 = r.left_reg ? ck.E[2] : ck.E[1];
-        const T v = mur ? (T)(c.e1 + (T)g.cm * (en1 - c.e0)) : (T)0;
+        const R en1 = r.left_reg ? ck.E[2] : ck.E[1];
+        const R v = mur ? (R)(c.e1 + (R)g.cm * (en1 - c.e0)) : (R)0;
         const bool here = lane == r.left_lane;
         ck.E[0] = (here && !r.left_reg) ? v : ck.E[0];
         ck.E[1] = (here && r.left_reg) ? v : ck.E[1];
@@ -426,11 +479,11 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, co
     }
     if constexpr ((RM & kRoleRight) != 0) {
         const int ir = r.right_reg;
-        const T prev = shfl_up1(ck.E[C - 1]);
-        const T left1 = upick<T, C>(ck.E, ir > 0 ? ir - 1 : 0);
-        const T en1 = ir > 0 ? left1 : prev;
-        const T v = mur ? (T)(c.eR1 + (T)g.cm * (en1 - c.eR)) : (T)0;
-        uput<T, C>(ck.E, ir, lane == r.right_lane, v);
+        const R prev = shfl_up1(ck.E[C - 1]);
+        const R left1 = upick<R, C>(ck.E, ir > 0 ? ir - 1 : 0);
+        const R en1 = ir > 0 ? left1 : prev;
+        const R v = mur ? (R)(c.eR1 + (R)g.cm * (en1 - c.eR)) : (R)0;
+        uput<R, C>(ck.E, ir, lane == r.right_lane, v);
         c.eR = v;
         c.eR1 = en1;
     }
@@ -512,8 +565,9 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
                                          int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
 {
     constexpr bool SRC = (RM & kRoleSrc) != 0;
-    EndCarry<T> c;
-    ends_init<T, C>(ck.E, r, c);
+    typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
+    EndCarry<R> c;
+    ends_init<R, C>(ck.E, r, c);
     for (int base = 0; base < nsteps; base += 64) {
         const int cnt = nsteps - base < 64 ? nsteps - base : 64;
         const int slot = slot0 + base;
@@ -524,14 +578,14 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
         }
         auto one = [&](int st) {
             const double sv = (SRC && r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
-            chunk_step<T, C, PLASMA, CPML, RM>(ck, g, r, lane, c, sv, er, hl);
+            chunk_step<T, C, PLASMA, CPML, RM, JF>(ck, g, r, lane, c, sv, er, hl);
             post(base + st);
             if constexpr ((RM & kRoleProbe) == 0) {
             } else if (wp.n > 2) {
-                wave_probes<T, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
+                wave_probes<R, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
             } else {
-                if (wp.n > 0) wave_probe_store<T, C>(g, wp.lane[0], wp.reg[0], wp.row[0], lane, ck.E, slot + st);
-                if (wp.n > 1) wave_probe_store<T, C>(g, wp.lane[1], wp.reg[1], wp.row[1], lane, ck.E, slot + st);
+                if (wp.n > 0) wave_probe_store<R, C>(g, wp.lane[0], wp.reg[0], wp.row[0], lane, ck.E, slot + st);
+                if (wp.n > 1) wave_probe_store<R, C>(g, wp.lane[1], wp.reg[1], wp.row[1], lane, ck.E, slot + st);
             }
         };
         int st = 0;

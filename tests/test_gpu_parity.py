@@ -1,9 +1,12 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 FP64 bar: ||X - X_oracle||_inf / ||X_oracle||_inf <= 1e-12 for the probe
-spectra and the same relative bound for final E, H, J.  The three execution
-modes (per-step, temporally blocked, resident) must agree bit for bit, and so
-must step(a) + step(b) with step(a + b).
+spectra and the same relative bound for final E, H, J.  In FP64 (and in the
+all-FP32 ablation) the execution modes (per-step, temporally blocked,
+resident, mixed) must agree bit for bit, and so must step(a) + step(b) with
+step(a + b).  FP32 storage rounds the FP64 register values where a launch
+stores them, so there each mode is held to the oracle instead, and a run of
+one launch must equal the FP64 run rounded once.
 """
 import sys
 import zlib
@@ -90,27 +93,54 @@ def test_c1_fp64_reflection_transmission(G):
     assert np.max(np.abs(np.abs(Tt) - np.abs(To))) <= TOL64
 
 
-def test_c1_fp32_error_stated(G):
-    """FP32 fields with FP64 coefficients, plasma updates and DFT: the |R|, |T|
-    error against the FP64 oracle, per band."""
-    p = W.slab_c1()
-    T = p.steps
-    say(f"case c1 two-run R/T fp32 steps={T}")
-    Ro, To, so, vo = oracle.reflect_transmit(p, T)
-    R, Tt, s, v = G.reflect_transmit(p, T, precision="f32")
+def rt_errors(p, R, Tt, s, Ro, To, so):
     dR = np.abs(np.abs(R) - np.abs(Ro))
     dT = np.abs(np.abs(Tt) - np.abs(To))
-    spec = relerr(s, so)
-    hi = p.freqs >= 12e9
-    say(f"fp32 c1: spectra {spec:.2e}  max|dR| {dR.max():.2e}  max|dT| {dT.max():.2e}  "
-        f"f>=12GHz: |dR| {dR[hi].max():.2e} |dT| {dT[hi].max():.2e}")
-    # FP32 storage rounds every update (6e-8 relative); the 4096-step window
-    # holds under 12 periods below 12 GHz, where the pulse spectrum is weak and
-    # the uniform static mode collects the rounding: there the error grows to
-    # a few 1e-4 at 1 GHz.
-    assert spec < 2e-5
-    assert dR[hi].max() < 1e-5 and dT[hi].max() < 1e-5
-    assert dR.max() < 5e-4 and dT.max() < 5e-4
+    return relerr(s, so), dR, dT
+
+
+def test_c1_fp32_error_stated(G):
+    """FP32 storage (FP64 registers, coefficients, plasma update and DFT): the
+    |R|, |T| error against the FP64 oracle at every one of the 256 frequencies
+    (1-100 GHz), for the executor AUTO picks (resident: the fields are rounded
+    to FP32 once per sample window) and, stated beside it, for the register
+    tiles (rounded once per 64-step launch) and the per-step kernels (rounded
+    every step)."""
+    p = W.slab_c1()
+    T = p.steps
+    Ro, To, so, vo = oracle.reflect_transmit(p, T)
+    res = {}
+    for ex in ("auto", "tiled", "step"):
+        say(f"case c1 two-run R/T fp32 exec={ex} steps={T}")
+        R, Tt, s, v = G.reflect_transmit(p, T, precision="f32", exec=ex)
+        spec, dR, dT = rt_errors(p, R, Tt, s, Ro, To, so)
+        res[ex] = (spec, dR.max(), dT.max())
+        say(f"fp32 c1 {ex}: spectra {spec:.2e}  max|dR| {dR.max():.2e}  max|dT| {dT.max():.2e}")
+    # the target, at all 256 frequencies
+    assert res["auto"][1] <= 1e-5 and res["auto"][2] <= 1e-5 and res["auto"][0] <= 1e-6
+    # stated: one rounding per launch collects in the modes open Mur ends do not
+    # damp (a CPU model of the same arithmetic puts 64-step launches at
+    # ~1e-5 and per-step rounding at ~7e-5 on this slab, at 1-3 GHz)
+    assert max(res["tiled"][1:]) <= 5e-5
+    assert max(res["step"][1:]) <= 3e-4
+
+
+def test_fp32_one_launch_is_fp64_rounded(G):
+    """A run that one launch covers (a resident window, or a tile pass of all
+    its steps): the FP32 probe samples are the FP64 register values, so the
+    spectra equal the FP64 run's bit for bit, and the stored E and H are the
+    FP64 fields rounded once to FP32."""
+    rng = np.random.default_rng(31)
+    probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 513, 1000, 3001)]
+    probs = [q.copy(freqs=probs[0].freqs) for q in probs]
+    for ex, T, kw in (("resident", 700, {}), ("tiled", 48, dict(tile_cells=512, steps_per_pass=48))):
+        say(f"case fp32 one launch {ex} steps={T}")
+        X64, F64 = gpu_run(G, probs, T, "f64", ex, **kw)
+        X32, F32 = gpu_run(G, probs, T, "f32", ex, **kw)
+        assert np.array_equal(X32, X64), ex
+        for b in range(len(probs)):
+            for k in ("E", "H"):
+                assert np.array_equal(F32[b][k], F64[b][k].astype(np.float32).astype(np.float64)), (ex, b, k)
 
 
 def test_c1_fp32_delta_ablation_error_stated(G):
@@ -135,9 +165,11 @@ def test_c1_fp32_delta_ablation_error_stated(G):
         h.run(1500)        # the pulse (half a node a step from node 100) is inside the slab
         J = h.fields()["J"]
     assert np.any(J != 0) and np.array_equal(J, J.astype(np.float32).astype(np.float64))
-    # measured on MI355X: spectra 9.5e-6, |dR| 5.0e-6 and |dT| 1.5e-6 at f >= 12 GHz
-    # (3.3e-4 and 7.9e-5 over 1-100 GHz), as close to the oracle as the FP32
-    # mode: FP32 storage of E and H, not the J arithmetic, sets the error here
+    # every field update rounded to FP32: measured on MI355X, spectra 9.5e-6,
+    # |dR| 5.0e-6 and |dT| 1.5e-6 at f >= 12 GHz but 3.3e-4 and 7.9e-5 over
+    # 1-100 GHz: the rounding of E and H after every operation, not the J
+    # arithmetic, sets this error (the FP32 mode, which rounds once a
+    # window, stays within 1e-5 everywhere)
     assert relerr(s, so) < 2e-5
     assert dR[hi].max() < 1e-5 and dT[hi].max() < 1e-5
     assert dR.max() < 5e-4 and dT.max() < 5e-4
@@ -173,22 +205,32 @@ def test_fp32_delta_tiles_match_per_step_bitwise(G, tile_cells):
 def test_role_groups_bitwise(G, precision):
     """A batch with more role tiles than the grouping threshold (2048): the
     role tiles are launched per role group (probe only, source, left end,
-    right end, left end with source, other) with the step compiled for each,
-    and give the bits of the per-step path."""
+    right end, left end with source, other) with the step compiled for each.
+    FP64: the bits of the per-step path.  FP32: the bits of each slab run on
+    its own (the same tiles and launches, its role tiles then in one small
+    class running the per-wave role code)."""
     rng = np.random.default_rng(23)
     probs = [W.random_slab(rng, int(n), n_freqs=4) for n in rng.integers(600, 1500, 1100)]
     probs = [q.copy(freqs=probs[0].freqs) for q in probs]
     T = 200
     say(f"case role groups {precision} slabs={len(probs)} steps={T}")
-    Xs, Fs = gpu_run(G, probs, T, precision, "step")
-    Xt, Ft = gpu_run(G, probs, T, precision, "tiled", tile_cells=512, steps_per_pass=48)
-    assert np.array_equal(Xt, Xs)
-    for b in range(0, len(probs), 37):
-        for k in ("E", "H", "J"):
-            assert np.array_equal(Ft[b][k], Fs[b][k]), (b, k)
+    kw = dict(tile_cells=512, steps_per_pass=48)
+    Xt, Ft = gpu_run(G, probs, T, precision, "tiled", **kw)
+    if precision == "f64":
+        Xs, Fs = gpu_run(G, probs, T, precision, "step")
+        assert np.array_equal(Xt, Xs)
+        for b in range(0, len(probs), 37):
+            for k in ("E", "H", "J"):
+                assert np.array_equal(Ft[b][k], Fs[b][k]), (b, k)
+    else:
+        for b in (0, 1, 555, 1099):
+            Xb, Fb = gpu_run(G, probs[b], T, precision, "tiled", **kw)
+            assert np.array_equal(Xt[b], Xb[0]), b
+            for k in ("E", "H", "J"):
+                assert np.array_equal(Ft[b][k], Fb[0][k]), (b, k)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", ["f64", "f32d"])
 def test_exec_modes_bitwise_identical(G, precision):
     rng = np.random.default_rng(21)
     probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 511, 512, 513, 1000, 2049, 3001)]
@@ -196,21 +238,42 @@ def test_exec_modes_bitwise_identical(G, precision):
     T = 700
     say(f"case exec-modes bitwise {precision} grids={[q.n for q in probs]} steps={T}")
     out = {}
-    for ex in EXECS:
+    execs = EXECS if precision == "f64" else ["step", "tiled"]
+    for ex in execs:
         X, F = gpu_run(G, probs, T, precision, ex)
         out[ex] = (X, F)
-    for ex in ("tiled", "resident"):
+    for ex in execs[1:]:
         assert np.array_equal(out[ex][0], out["step"][0]), ex
         for b in range(len(probs)):
             for k in ("E", "H", "J"):
                 assert np.array_equal(out[ex][1][b][k], out["step"][1][b][k]), (ex, b, k)
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_mixed_executor_bitwise(G, precision):
+@pytest.mark.parametrize("ex", EXECS + ["mixed"])
+def test_fp32_exec_modes_match_oracle(G, ex):
+    """FP32 storage on every executor: spectra against the FP64 oracle within
+    the error each mode's rounding points leave (per-step rounding the
+    largest), fields to the same level of the pulse scale."""
+    rng = np.random.default_rng(21)
+    probs = [W.random_slab(rng, n, n_freqs=8) for n in (37, 511, 512, 513, 1000, 2049, 3001)]
+    probs = [q.copy(freqs=probs[0].freqs) for q in probs]
+    T = 700
+    say(f"case fp32 exec={ex} vs oracle grids={[q.n for q in probs]} steps={T}")
+    X, F = gpu_run(G, probs, T, "f32", ex)
+    tol = 1e-5 if ex == "step" else 2e-6
+    for b, q in enumerate(probs):
+        ref = oracle.run(q, T)
+        e = relerr(X[b], ref["X"])
+        f = max(field_errs(F[b], ref, q.n, q.wp2, q.dt))
+        say(f"fp32 {ex} grid {b} n={q.n}: spectra {e:.2e} fields {f:.2e}")
+        assert e <= tol and f <= 20 * tol, b
+
+
+def test_mixed_executor_bitwise(G):
     """Uneven batch across the resident limit (4096 nodes): grids that fit run
     as resident bins, the others as tiles, in the same passes; bit for bit the
     per-step executor, and the oracle within 1e-12 (FP64)."""
+    precision = "f64"
     rng = np.random.default_rng(23)
     probs = [W.random_slab(rng, n, n_freqs=6) for n in (37, 513, 4095, 4096, 4097, 5000, 8128)]
     probs = [q.copy(freqs=probs[0].freqs) for q in probs]
@@ -224,10 +287,9 @@ def test_mixed_executor_bitwise(G, precision):
         for k in ("E", "H", "J"):
             assert np.array_equal(Fm[b][k], Fs[b][k]), (b, k)
             assert np.array_equal(Fa[b][k], Fs[b][k]), (b, k)
-    if precision == "f64":
-        for b in (0, 4, 6):
-            Xo = oracle.run(probs[b], T)["X"]
-            assert np.max(np.abs(Xm[b] - Xo)) <= 1e-12 * np.max(np.abs(Xo)), b
+    for b in (0, 4, 6):
+        Xo = oracle.run(probs[b], T)["X"]
+        assert np.max(np.abs(Xm[b] - Xo)) <= 1e-12 * np.max(np.abs(Xo)), b
 
 
 @pytest.mark.parametrize("ex", EXECS + ["mixed"])
