@@ -18,6 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRCS = ["rketd1d.c", "adjoint1d.c", "rketd3d.c"]
 _lib = None
+# timing builds of the same sources (the benchmark's CPU-baseline leg only):
+# "native" is the serial oracle with -O3 -march=native, "omp" adds -fopenmp
+# (the 1D node loops carry OpenMP pragmas, ignored by the other builds).
+# Every build keeps -ffp-contract=off, so all give the same results.
+_TIMING = {"native": ["-O3", "-march=native"], "omp": ["-O3", "-march=native", "-fopenmp"]}
+_timing_libs = {}
 
 BC = {"mur": 0, "cpml": 1, "pec": 2, "periodic": 3}
 
@@ -33,7 +39,21 @@ def build(out: str = _SO, extra: Optional[list] = None) -> str:
     return out
 
 
-def lib():
+def timing_lib(kind: str):
+    """The "native" or "omp" timing build (built on first use, under /tmp)."""
+    if kind not in _timing_libs:
+        import tempfile
+        out = os.path.join(tempfile.gettempdir(), f"liboracle_{kind}_{os.getpid()}.so")
+        build(out, _TIMING[kind])
+        L = ctypes.CDLL(out)
+        _declare(L)
+        _timing_libs[kind] = L
+    return _timing_libs[kind]
+
+
+def lib(kind: Optional[str] = None):
+    if kind is not None:
+        return timing_lib(kind)
     global _lib
     if _lib is None:
         srcs = [os.path.join(_HERE, s) for s in _SRCS if os.path.exists(os.path.join(_HERE, s))]
@@ -165,8 +185,9 @@ def check(p) -> int:
     return lib().or1d_check(ctypes.byref(pb))
 
 
-def run(p, nsteps: int, state: Optional[dict] = None) -> dict:
-    """Advance `state` (default: zero fields at step 0) by nsteps; returns a new dict."""
+def run(p, nsteps: int, state: Optional[dict] = None, kind: Optional[str] = None) -> dict:
+    """Advance `state` (default: zero fields at step 0) by nsteps; returns a new
+    dict.  kind: a timing build ("native", "omp") instead of the plain one."""
     st = new_state(p) if state is None else {k: (v.copy() if isinstance(v, np.ndarray) else v)
                                             for k, v in state.items()}
     keep = _Keep()
@@ -178,7 +199,7 @@ def run(p, nsteps: int, state: Optional[dict] = None) -> dict:
     cs = _State(E=_ptr(st["E"]), H=_ptr(st["H"]), J=_ptr(st["J"]),
                 psiE=_ptr(st["psiE"]), psiH=_ptr(st["psiH"]),
                 Xre=_ptr(Xre), Xim=_ptr(Xim), step=st["step"])
-    rc = lib().or1d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
+    rc = lib(kind).or1d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
     if rc != 0:
         raise ValueError(f"oracle rejected the problem (code {rc})")
     st["X"] = Xre + 1j * Xim
@@ -206,7 +227,7 @@ def adjoint_step(p, lE, lH, lJ):
     return lE, lH, lJ
 
 
-def adjoint_r2(p, nsteps: int, xv: np.ndarray, probe: int = 0):
+def adjoint_r2(p, nsteps: int, xv: np.ndarray, probe: int = 0, kind: Optional[str] = None):
     """L = sum_f |(X_f - xv_f)/xv_f|^2 at probe `probe`, and dL/d wp2 (full trajectory)."""
     keep = _Keep()
     pb = _problem(p, keep)
@@ -216,7 +237,7 @@ def adjoint_r2(p, nsteps: int, xv: np.ndarray, probe: int = 0):
     grad = np.zeros(p.n)
     F = len(p.freqs)
     X = np.zeros(2 * F)
-    rc = lib().or1d_adjoint_r2(ctypes.byref(pb), nsteps, probe, _ptr(xr), _ptr(xi),
+    rc = lib(kind).or1d_adjoint_r2(ctypes.byref(pb), nsteps, probe, _ptr(xr), _ptr(xi),
                                ctypes.addressof(loss), _ptr(grad), _ptr(X))
     if rc != 0:
         raise ValueError(f"oracle adjoint rejected the problem (code {rc})")
@@ -284,7 +305,7 @@ def check3(p) -> int:
     return lib().or3d_check(ctypes.byref(_problem3(p, keep)))
 
 
-def run3d(p, nsteps: int, state: Optional[dict] = None) -> dict:
+def run3d(p, nsteps: int, state: Optional[dict] = None, kind: Optional[str] = None) -> dict:
     """Advance a 3D state (default: zero fields at step 0) by nsteps; returns a
     new dict with E, H, J [3, nx, ny, nz], psi, Einc, Hinc, X [points, freqs]."""
     st = new_state3(p) if state is None else {k: (v.copy() if isinstance(v, np.ndarray) else v)
@@ -300,7 +321,7 @@ def run3d(p, nsteps: int, state: Optional[dict] = None) -> dict:
                  psi=_ptr(st["psi"]) if p.cpml > 0 else None,
                  Einc=_ptr(st["Einc"]), Hinc=_ptr(st["Hinc"]),
                  Xre=_ptr(Xre), Xim=_ptr(Xim), step=st["step"])
-    rc = lib().or3d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
+    rc = lib(kind).or3d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
     if rc != 0:
         raise ValueError(f"3D oracle rejected the problem (code {rc})")
     st["X"] = Xre + 1j * Xim

@@ -236,7 +236,9 @@ int or1d_step(const or1d_problem *pb, or1d_state *st, int64_t nsteps)
         double *E = st->E, *H = st->H, *J = st->J;
         const double E0 = E[0], E1 = E[1], Em2 = E[n - 2], Em1 = E[n - 1];
 
-        /* H^{n+1/2} from E^n, eq.(14) */
+        /* H^{n+1/2} from E^n, eq.(14) (every node independent: the OpenMP
+           pragmas only matter in the context-timing build, -fopenmp) */
+#pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < nH; ++k) {
             double dE = E[(k + 1) % n] - E[k];
             if (cpml) {
@@ -247,6 +249,7 @@ int or1d_step(const or1d_problem *pb, or1d_state *st, int64_t nsteps)
             }
         }
         /* E^{n+1} from E^n, J^n, H^{n+1/2}: eqs.(11)+(12) solved together */
+#pragma omp parallel for schedule(static)
         for (int64_t k = e_lo; k < e_hi; ++k) {
             const double *c = cf + 9 * k;
             double curl = H[k] - H[(k - 1 + n) % n];
@@ -263,6 +266,7 @@ int or1d_step(const or1d_problem *pb, or1d_state *st, int64_t nsteps)
             E[pb->src_cell] += or_source(t, pb->src_tau, pb->src_t0, pb->src_amp);
         }
         /* J^{n+1}, eq.(11); in vacuum b1 = b2 = 0 and J stays at zero */
+#pragma omp parallel for schedule(static)
         for (int64_t k = e_lo; k < e_hi; ++k) {
             const double *c = cf + 9 * k;
             J[k] = c[0] * J[k] + c[7] * Eold[k] + c[8] * E[k];

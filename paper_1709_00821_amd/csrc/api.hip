@@ -132,6 +132,7 @@ struct fdtd_plasma {
     int64_t ck_n = 0;          // checkpoint slots (steps 0, s, 2s, ...)
     bool ck_on = false;        // the advance in progress stores checkpoints
     bool ck_valid = false;     // the state is a checkpointed run() of ck_run steps
+    bool tmp_valid = false;    // d_Xtmp holds the spectra of the current state (run() folds them)
     int64_t ck_run = 0;
     char *d_ck = nullptr;      // [ck_n][3][slot_bytes]: E, H, J
     char *d_seg = nullptr;     // [ck_s + 1][3][slot_bytes]
@@ -562,6 +563,8 @@ void zero_state(fdtd_plasma *h)
     launch_fill(h->d_X, 16 * h->batch * h->P * (int64_t)h->F, h->stream);
 }
 
+void spectra_to_tmp(fdtd_plasma *h);
+
 void reset(fdtd_plasma *h)
 {
     if (h->esize == 8) zero_state<double>(h); else zero_state<float>(h);
@@ -935,6 +938,7 @@ int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps)
     if (rc) return rc;
     if (nsteps < 0) return fail(FDTD_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
     if (nsteps > 0) h->ck_valid = false;
+    h->tmp_valid = false;
     return advance(h, nsteps);
 }
 
@@ -945,10 +949,15 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
     if (nsteps < 0) return fail(FDTD_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
     h->ck_on = h->d_ck != nullptr && nsteps <= h->ck_T;
     h->ck_valid = false;
+    h->tmp_valid = false;
     if (h->stream == nullptr) {
         // the legacy null stream cannot be captured: run eagerly
         reset(h);
         rc = advance(h, nsteps);
+        if (rc == FDTD_OK && nsteps > 0) {
+            spectra_to_tmp(h);
+            h->tmp_valid = true;
+        }
         h->ck_valid = h->ck_on && rc == FDTD_OK;
         h->ck_run = nsteps;
         h->ck_on = false;
@@ -961,6 +970,10 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
         HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
         reset(h);
         rc = advance(h, nsteps);
+        // the run's last, partially filled sample window is folded into the
+        // spectra inside the run (into d_Xtmp, so the running sums of d_X stay
+        // as a later step() continuing the window expects them)
+        if (rc == FDTD_OK && nsteps > 0) spectra_to_tmp(h);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(h->stream, &graph);
         if (rc) { h->ck_on = false; if (graph) (void)hipGraphDestroy(graph); return rc; }
@@ -991,6 +1004,7 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps)
         }
     }
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
+    h->tmp_valid = nsteps > 0;
     h->ck_valid = h->ck_on;
     h->ck_run = nsteps;
     h->ck_on = false;
@@ -1013,11 +1027,9 @@ int fdtd_plasma_probe_spectra(fdtd_plasma *h, double *re, double *im)
     if (!re || !im) return fail(FDTD_E_INVALID, "output pointer is NULL");
     if (h->steps == 0) return fail(FDTD_E_STATE, "no step taken yet");
     const int64_t rows = h->batch * h->P, nX = rows * h->F;
-    // X plus the partial window, without disturbing the running sums
-    HIP_TRY(hipMemcpyAsync(h->d_Xtmp, h->d_X, 16 * nX, hipMemcpyDeviceToDevice, h->stream));
-    const int count = (int)(h->steps - h->win_base);
-    launch_dft(h->grids(), h->d_freqs, h->F, h->win_base + 1, count, h->d_tw, h->d_Xtmp, rows,
-               h->stream);
+    // X plus the partial window, without disturbing the running sums (run()
+    // has folded it already)
+    if (!h->tmp_valid) spectra_to_tmp(h);
     std::vector<double2> X(nX);
     HIP_TRY(hipMemcpyAsync(X.data(), h->d_Xtmp, 16 * nX, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1071,7 +1083,7 @@ namespace {
 void spectra_to_tmp(fdtd_plasma *h)
 {
     const int64_t rows = h->batch * h->P, nX = rows * h->F;
-    (void)hipMemcpyAsync(h->d_Xtmp, h->d_X, 16 * nX, hipMemcpyDeviceToDevice, h->stream);
+    launch_copy(h->d_Xtmp, h->d_X, 16 * nX, h->stream);   // a kernel: capturable
     const int count = (int)(h->steps - h->win_base);
     launch_dft(h->grids(), h->d_freqs, h->F, h->win_base + 1, count, h->d_tw, h->d_Xtmp, rows,
                h->stream);

@@ -27,13 +27,13 @@ def _bucket(n: int, batched: bool = False) -> str:
 
 def pick(precision: str, n: int, tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0,
          batched: bool = False) -> dict:
-    if precision == "f32d":    # the FP32 ablation runs the FP32 tile shapes
-        precision = "f32"
     out = dict(DEFAULT)
     if os.path.exists(CACHE):
         try:
-            table = json.load(open(CACHE))
-            ent = table.get("gfx950", {}).get(precision, {}).get(_bucket(n, batched))
+            table = json.load(open(CACHE)).get("gfx950", {})
+            ent = table.get(precision, {}).get(_bucket(n, batched))
+            if ent is None and precision == "f32d":   # the FP32 ablation, untuned: the FP32 shapes
+                ent = table.get("f32", {}).get(_bucket(n, batched))
             if ent:
                 out.update({k: int(ent[k]) for k in ("tile_cells", "steps_per_pass", "tile_waves") if k in ent})
         except (OSError, ValueError, KeyError):
@@ -97,7 +97,7 @@ def sweep(precision: str, n: int = 1 << 22, steps: int = 2000, reps: int = 2,
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="sweep launch shapes and record the best")
-    ap.add_argument("--precision", nargs="+", default=["f32", "f64"])
+    ap.add_argument("--precision", nargs="+", default=["f32", "f64", "f32d"])
     ap.add_argument("--workload", nargs="+", default=["large", "batched", "small"],
                     choices=["large", "batched", "small"])
     ap.add_argument("--cells", type=int, default=1 << 22)

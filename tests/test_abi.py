@@ -221,3 +221,17 @@ def test_fp32_delta_ablation_plans(L):
         d, keep = _desc(p, precision="f32d", **kw)
         assert _code(d)[0] == -1, kw
         assert b"FDTD_F32_DELTA" in L.lib().fdtd_plasma_last_error()
+
+
+def test_grid_length_limit(L):
+    """Tiles address nodes with 32-bit indices: a grid of 2^31 nodes is
+    rejected (before any node array is read)."""
+    p = W.slab_c1(n=64, slab=(20, 30), src=10, probes=(5, 50))
+    d, keep = _desc(p)
+    big = np.array([1 << 31], np.int64)
+    d.cells = big.ctypes.data
+    rc, _ = _code(d)
+    assert rc == -1
+    msg = L.lib().fdtd_plasma_last_error()
+    msg = msg.decode() if isinstance(msg, bytes) else str(msg)
+    assert "2^31 - 1" in msg
