@@ -81,6 +81,8 @@ enum { FDTD_EXEC_AUTO = 0, FDTD_EXEC_STEP = 1, FDTD_EXEC_TILED = 2, FDTD_EXEC_RE
 
 /* flags */
 #define FDTD_FLAG_CHECKPOINT 0x1   /* run() stores sqrt(T)-spaced checkpoints for the adjoint */
+#define FDTD_FLAG_RECORD 0x2       /* keep every probe sample of the first record_steps steps
+                                      (fdtd_plasma_probe_series, fdtd_plasma_probe_fft) */
 
 typedef struct {
     uint32_t struct_size;        /* sizeof(fdtd_plasma_desc) */
@@ -128,7 +130,9 @@ typedef struct {
     int32_t tile_waves;          /* TILED: waves per tile (1, 2, 4 or 8; neighbouring waves of a
                                     tile exchange edge values through LDS every step, so the
                                     halo is paid once per tile_waves*tile_cells nodes); 0 = default */
-    int32_t reserved;
+    int32_t record_steps;        /* with FDTD_FLAG_RECORD: steps whose probe samples are kept,
+                                    in [1, 2^24]; the FFT takes up to 2 * next_pow2(record_steps + 1)
+                                    points.  Costs 8 B + 64 B per probe and step of device memory. */
     void *stream;                /* hipStream_t for every launch and copy; NULL = null stream */
 } fdtd_plasma_desc;
 
@@ -152,8 +156,10 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace,
 
 /*
  * Advance every grid by nsteps (>= 0) time steps, asynchronously on the
- * handle's stream.  step(a) followed by step(b) gives bit-for-bit the same
- * state and spectra as step(a + b).
+ * handle's stream.  In FDTD_F64 and FDTD_F32_DELTA, step(a) followed by
+ * step(b) gives bit-for-bit the same state and spectra as step(a + b); in
+ * FDTD_F32 the fields are rounded to FP32 where each launch ends, so the two
+ * agree to that rounding.
  */
 int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps);
 
@@ -171,6 +177,25 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps);
  * FDTD_E_NONFINITE if any value is NaN or Inf (the values are still copied).
  */
 int fdtd_plasma_probe_spectra(fdtd_plasma *h, double *re, double *im);
+
+/*
+ * The recorded probe series (section IV-B records the probe field over the
+ * run and Fourier transforms it): host out[batch][n_probes][steps] doubles,
+ * out[b][p][m-1] = E^m at probe p of grid b for m = 1 .. steps, steps the
+ * steps done since create or the last run().  Waits for the stream.  Needs
+ * FDTD_FLAG_RECORD and 1 <= steps <= record_steps, else FDTD_E_STATE.
+ */
+int fdtd_plasma_probe_series(fdtd_plasma *h, double *out);
+
+/*
+ * FFT of the recorded series, zero-padded to nfft points (a power of 2 with
+ * steps < nfft <= 2 * next_pow2(record_steps + 1)), computed on the device:
+ *   X[b][p][k] = dt sum_{m=1}^{steps} E^m[p] exp(-j 2 pi k m / nfft),  k < nfft,
+ * the running DFT's sum at f_k = k / (nfft dt).  Host outputs re, im of
+ * [batch][n_probes][nfft] doubles; waits for the stream.  FDTD_E_STATE as
+ * for fdtd_plasma_probe_series, FDTD_E_INVALID for another nfft.
+ */
+int fdtd_plasma_probe_fft(fdtd_plasma *h, int64_t nfft, double *re, double *im);
 
 /*
  * Copy one grid's state to host arrays (doubles, waiting for the stream):

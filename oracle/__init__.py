@@ -207,6 +207,28 @@ def run(p, nsteps: int, state: Optional[dict] = None, kind: Optional[str] = None
     return st
 
 
+def probe_series(p, nsteps: int) -> np.ndarray:
+    """E^m at every probe for m = 1 .. nsteps, [n_probes, nsteps]: the oracle
+    advanced one step at a time (section IV-B records the probe field over
+    the run)."""
+    st = new_state(p)
+    out = np.zeros((len(p.probes), nsteps))
+    for m in range(nsteps):
+        st = run(p, 1, st)
+        out[:, m] = st["E"][np.asarray(p.probes)]
+    return out
+
+
+def series_fft(series: np.ndarray, nfft: int, dt: float) -> np.ndarray:
+    """X[k] = dt sum_{m=1}^{T} E^m exp(-j 2 pi k m / nfft) of series [..., T]
+    (entry m-1 is E^m), zero-padded to nfft points: numpy's FFT of the
+    sequence 0, E^1, .., E^T, 0, .. (the running DFT at f = k / (nfft dt))."""
+    T = series.shape[-1]
+    x = np.zeros(series.shape[:-1] + (nfft,))
+    x[..., 1:T + 1] = series
+    return dt * np.fft.fft(x, axis=-1)
+
+
 def reflect_transmit(p, nsteps: int, refl: int = 0, trans: int = 1):
     """Two-run R and T: R = (X_refl - X_refl^vac)/X_refl^vac, T = X_trans/X_trans^vac."""
     s = run(p, nsteps)["X"]

@@ -24,6 +24,7 @@ F64, F32, F32_DELTA = 0, 1, 2
 BC = {"mur": 0, "cpml": 1, "pec": 2}
 EXEC = {"auto": 0, "step": 1, "tiled": 2, "resident": 3, "mixed": 4}
 FLAG_CHECKPOINT = 0x1
+FLAG_RECORD = 0x2
 
 
 class FdtdError(RuntimeError):
@@ -61,7 +62,7 @@ class Desc(ctypes.Structure):
         ("steps_per_pass", ctypes.c_int32),
         ("checkpoint_steps", ctypes.c_int32),
         ("tile_waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("record_steps", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -115,6 +116,8 @@ def lib():
             "fdtd_plasma_step": [p, i64],
             "fdtd_plasma_run": [p, i64],
             "fdtd_plasma_probe_spectra": [p, p, p],
+            "fdtd_plasma_probe_series": [p, p],
+            "fdtd_plasma_probe_fft": [p, i64, p, p],
             "fdtd_plasma_get_fields": [p, i64, p, p, p],
             "fdtd_plasma_steps_done": [p, p],
             "fdtd_plasma_grad_r2": [p, i64, i32, p, p, p, p],

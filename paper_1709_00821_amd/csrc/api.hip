@@ -134,6 +134,11 @@ struct fdtd_plasma {
     bool ck_valid = false;     // the state is a checkpointed run() of ck_run steps
     bool tmp_valid = false;    // d_Xtmp holds the spectra of the current state (run() folds them)
     int64_t ck_run = 0;
+    // recorded probe series (FDTD_FLAG_RECORD)
+    int64_t rec_R = 0;         // steps kept per series row
+    int64_t nfft_max = 0;
+    double *d_series = nullptr;    // [batch * P][rec_R]
+    double2 *d_fft[2] = {nullptr, nullptr};   // [batch * P][nfft_max] ping-pong
     char *d_ck = nullptr;      // [ck_n][3][slot_bytes]: E, H, J
     char *d_seg = nullptr;     // [ck_s + 1][3][slot_bytes]
     void *d_lam[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
@@ -269,7 +274,10 @@ int validate(const fdtd_plasma_desc *d)
     }
     if ((d->flags & FDTD_FLAG_CHECKPOINT) && (d->checkpoint_steps < 1 || d->checkpoint_steps > (1 << 30)))
         return fail(FDTD_E_INVALID, "checkpoint_steps %d out of [1, 2^30]", d->checkpoint_steps);
-    if (d->flags & ~FDTD_FLAG_CHECKPOINT) return fail(FDTD_E_INVALID, "unknown flags 0x%x", d->flags);
+    if ((d->flags & FDTD_FLAG_RECORD) && (d->record_steps < 1 || d->record_steps > (1 << 24)))
+        return fail(FDTD_E_INVALID, "record_steps %d out of [1, 2^24]", d->record_steps);
+    if (d->flags & ~(FDTD_FLAG_CHECKPOINT | FDTD_FLAG_RECORD))
+        return fail(FDTD_E_INVALID, "unknown flags 0x%x", d->flags);
     if (d->tile_cells != 0 && (d->tile_cells % 256 != 0 || d->tile_cells < 256 || d->tile_cells > 1024))
         return fail(FDTD_E_INVALID, "tile_cells %d: must be 0, 256, 512, 768 or 1024", d->tile_cells);
     if (d->tile_waves != 0 && d->tile_waves != 1 && d->tile_waves != 2 && d->tile_waves != 4 && d->tile_waves != 8)
@@ -293,6 +301,7 @@ struct Plan {
     int64_t o_ck = 0, o_seg = 0, o_lam[2][3] = {{0, 0, 0}, {0, 0, 0}}, o_grad = 0, o_tab = 0,
             o_gsrc = 0, o_loss = 0, o_xref = 0, o_G = 0;
     int64_t ck_T = 0, ck_s = 0, ck_n = 0;
+    int64_t rec_R = 0, nfft_max = 0, o_series = 0, o_fft[2] = {0, 0};
     int64_t nodes = 0, state_bytes = 0, psi_bytes = 0;
     int SB = 0;
     std::vector<int64_t> off;
@@ -545,6 +554,14 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         p.o_rev_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.rev_tiles.size()));
         p.o_adj_srcv = L.take(8 * p.ck_s);
     }
+    if (d->flags & FDTD_FLAG_RECORD) {
+        p.rec_R = d->record_steps;
+        int64_t q = 1;
+        while (q < p.rec_R + 1) q <<= 1;
+        p.nfft_max = 2 * q;
+        p.o_series = L.take(8 * d->batch * P * p.rec_R);
+        for (int i = 0; i < 2; ++i) p.o_fft[i] = L.take(16 * d->batch * P * p.nfft_max);
+    }
     p.o_tiles = L.take((int64_t)sizeof(Tile) * std::max<size_t>(1, p.tiles.size()));
     p.o_slots = L.take((int64_t)sizeof(ResidentSlot) * std::max<size_t>(1, p.slots.size()));
     return FDTD_OK;
@@ -608,9 +625,19 @@ void launch_class(fdtd_plasma *h, const Grids &g, State<T> &s, int cur, int c, i
     }
 }
 
-// Fold the full sample window into X.
+// Copy the samples of the current window (full or partial) into the
+// recorded series.
+void record_window(fdtd_plasma *h)
+{
+    if (h->d_series)
+        launch_series_copy(h->d_samp, h->SB, h->batch * h->P, (int)(h->steps - h->win_base), h->d_series,
+                           h->rec_R, h->win_base, h->stream);
+}
+
+// Fold the full sample window into X (and into the recorded series).
 void flush(fdtd_plasma *h)
 {
+    record_window(h);
     const int count = (int)(h->steps - h->win_base);
     prof_begin(h, "dft_flush", 0);
     launch_dft(h->grids(), h->d_freqs, h->F, h->win_base + 1, count, h->d_tw, h->d_X,
@@ -866,6 +893,12 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         h->d_tab = (double *)(w + p.o_tab);
         h->d_gsrc = (double *)(w + p.o_gsrc);
     }
+    if (desc->flags & FDTD_FLAG_RECORD) {
+        h->rec_R = p.rec_R;
+        h->nfft_max = p.nfft_max;
+        h->d_series = (double *)(w + p.o_series);
+        for (int i = 0; i < 2; ++i) h->d_fft[i] = (double2 *)(w + p.o_fft[i]);
+    }
     h->d_tiles = (Tile *)(w + p.o_tiles);
     if (p.o_adj_tiles) {
         h->d_adj_tiles = (Tile *)(w + p.o_adj_tiles);
@@ -1040,6 +1073,53 @@ int fdtd_plasma_probe_spectra(fdtd_plasma *h, double *re, double *im)
         finite = finite && std::isfinite(X[i].x) && std::isfinite(X[i].y);
     }
     if (!finite) return fail(FDTD_E_NONFINITE, "a probe spectrum holds NaN or Inf");
+    return FDTD_OK;
+}
+
+int fdtd_plasma_probe_series(fdtd_plasma *h, double *out)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!out) return fail(FDTD_E_INVALID, "output pointer is NULL");
+    if (!h->d_series) return fail(FDTD_E_STATE, "created without FDTD_FLAG_RECORD");
+    if (h->steps < 1 || h->steps > h->rec_R)
+        return fail(FDTD_E_STATE, "%lld steps done, the series holds 1 .. %lld", (long long)h->steps,
+                    (long long)h->rec_R);
+    const int64_t rows = h->batch * h->P;
+    record_window(h);   // the partially filled window (its samples stay buffered)
+    std::vector<double> buf(rows * h->rec_R);
+    HIP_TRY(hipMemcpyAsync(buf.data(), h->d_series, 8 * rows * h->rec_R, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int64_t r = 0; r < rows; ++r)
+        std::memcpy(out + r * h->steps, buf.data() + r * h->rec_R, 8 * h->steps);
+    return FDTD_OK;
+}
+
+int fdtd_plasma_probe_fft(fdtd_plasma *h, int64_t nfft, double *re, double *im)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!re || !im) return fail(FDTD_E_INVALID, "output pointer is NULL");
+    if (!h->d_series) return fail(FDTD_E_STATE, "created without FDTD_FLAG_RECORD");
+    if (h->steps < 1 || h->steps > h->rec_R)
+        return fail(FDTD_E_STATE, "%lld steps done, the series holds 1 .. %lld", (long long)h->steps,
+                    (long long)h->rec_R);
+    if (nfft <= h->steps || nfft > h->nfft_max || (nfft & (nfft - 1)) != 0)
+        return fail(FDTD_E_INVALID, "nfft %lld: a power of 2 in (%lld, %lld]", (long long)nfft,
+                    (long long)h->steps, (long long)h->nfft_max);
+    const int64_t rows = h->batch * h->P;
+    record_window(h);
+    double2 *res = launch_fft(h->d_series, h->rec_R, rows, h->steps, nfft, h->d.dt, h->d_fft[0], h->d_fft[1],
+                              h->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FDTD_E_DEVICE, "FFT launch failed: %s", hipGetErrorString(e));
+    std::vector<double2> X(rows * nfft);
+    HIP_TRY(hipMemcpyAsync(X.data(), res, 16 * rows * nfft, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < rows * nfft; ++i) {
+        re[i] = X[i].x;
+        im[i] = X[i].y;
+    }
     return FDTD_OK;
 }
 

@@ -167,6 +167,15 @@ void launch_dft(const Grids &g, const double *freqs, int F, int64_t m_first, int
                 double2 *tw, double2 *X, int64_t rows, hipStream_t st);
 
 void launch_fill(void *p, int64_t bytes, hipStream_t st);
+
+// ---- recorded series and FFT (fft1d.hip) ----------------------------------
+// series[row][m0 + i] = samp[row][i] (i < count, m0 + i < R)
+void launch_series_copy(const double *samp, int SB, int64_t rows, int count, double *series, int64_t R,
+                        int64_t m0, hipStream_t st);
+// dt-scaled zero-padded FFT (nfft points) of the first `steps` entries of every
+// series row (entry m-1 at time m); returns the one of buf0, buf1 holding it
+double2 *launch_fft(const double *series, int64_t R, int64_t rows, int64_t steps, int64_t nfft, double dt,
+                    double2 *buf0, double2 *buf1, hipStream_t st);
 // srcv[i] = source value of step m_first + i, i < count (eq.(15) at t = m dt)
 void launch_src_table(const Grids &g, int64_t m_first, int count, double *srcv, hipStream_t st);
 

@@ -22,7 +22,7 @@ def _as_list(problems) -> List[Problem1D]:
 
 def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: int = 0,
               steps_per_pass: int = 0, checkpoint: int = 0, stream_handle: int = 0,
-              tile_waves: int = 0):
+              tile_waves: int = 0, record: int = 0):
     """Build the C descriptor; returns (desc, arrays it points into)."""
     probs = _as_list(problems)
     p0 = probs[0]
@@ -48,8 +48,9 @@ def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: 
     d.scheme = p0.scheme
     d.bc = L.BC[p0.bc]
     d.exec = L.EXEC[exec]
-    d.flags = L.FLAG_CHECKPOINT if checkpoint else 0
+    d.flags = (L.FLAG_CHECKPOINT if checkpoint else 0) | (L.FLAG_RECORD if record else 0)
     d.checkpoint_steps = int(checkpoint) if checkpoint else 0
+    d.record_steps = int(record) if record else 0
     d.batch = len(probs)
     d.cells = cells.ctypes.data
     d.dz, d.dt = p0.dz, p0.dt
@@ -80,7 +81,7 @@ class FdtdPlasma:
     def __init__(self, problems: Union[Problem1D, Sequence[Problem1D]], precision: str = "f64",
                  exec: str = "auto", tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0,
                  checkpoint: int = 0, stream: Optional[torch.cuda.Stream] = None,
-                 device: Union[int, str, torch.device] = "cuda"):
+                 device: Union[int, str, torch.device] = "cuda", record: int = 0):
         probs = _as_list(problems)
         self.problems = probs
         self.device = torch.device(device)
@@ -88,7 +89,7 @@ class FdtdPlasma:
         self.cells = np.array([q.n for q in probs], np.int64)
         self.offsets = np.concatenate([[0], np.cumsum(self.cells)])
         d, self._keep = make_desc(probs, precision, exec, tile_cells, steps_per_pass, checkpoint,
-                                  self.stream.cuda_stream, tile_waves)
+                                  self.stream.cuda_stream, tile_waves, record)
         self.desc = d
         self.precision = precision
         self.workspace_bytes = workspace_bytes(d)
@@ -124,6 +125,23 @@ class FdtdPlasma:
         if not (allow_nonfinite and rc == L.E_NONFINITE):
             L.check(rc)
         return (re + 1j * im).reshape(B, P, F)
+
+    def series(self) -> np.ndarray:
+        """Recorded probe samples (record=steps at construction), float64
+        [batch, n_probes, steps]: entry m-1 is E^m."""
+        B, P, T = len(self.problems), self.desc.n_probes, self.steps_done()
+        out = np.zeros(B * P * T)
+        L.check(L.lib().fdtd_plasma_probe_series(self.h, out.ctypes.data))
+        return out.reshape(B, P, T)
+
+    def fft(self, nfft: int) -> np.ndarray:
+        """dt-scaled FFT of the recorded series zero-padded to nfft points,
+        complex [batch, n_probes, nfft] (bin k at f = k / (nfft dt))."""
+        B, P = len(self.problems), self.desc.n_probes
+        re = np.zeros(B * P * nfft)
+        im = np.zeros(B * P * nfft)
+        L.check(L.lib().fdtd_plasma_probe_fft(self.h, int(nfft), re.ctypes.data, im.ctypes.data))
+        return (re + 1j * im).reshape(B, P, nfft)
 
     def fields(self, grid: int = 0) -> dict:
         n = int(self.cells[grid])

@@ -439,3 +439,38 @@ def test_adjoint_gradient_matches_central_differences():
         lm = loss(wp)
         fd = (lp - lm) / (2 * hk)
         assert abs(g[k] - fd) <= 1e-5 * abs(fd), (k, g[k], fd)
+
+
+def test_etd1_first_order_convergence_to_closed_form():
+    """eq.(9) (first-order exponential update of J): halving dz and dt (dt =
+    dz/(2c)) halves the gap to the closed-form slab, at 5 - 60 GHz, where
+    eq.(11) quarters it (the test above)."""
+    errs = []
+    for s in (1, 2):
+        p = W.slab_c1(n=1000 * s, dz=75e-6 / s, slab=(400 * s, 520 * s), src=100 * s,
+                      probes=(50 * s, 900 * s), n_freqs=12)
+        p = p.copy(freqs=np.linspace(5e9, 60e9, 12), scheme=2)
+        R, T, _, _ = oracle.reflect_transmit(p, (1 << 15) * s)
+        Ra, Ta = Z.drude_slab(p.freqs, (2 * math.pi * 28.7e9) ** 2, 2e10, 120 * 75e-6)
+        errs.append((np.max(np.abs(np.abs(R) - np.abs(Ra))), np.max(np.abs(np.abs(T) - np.abs(Ta)))))
+    r = np.array(errs[0]) / np.array(errs[1])
+    assert np.all(r > 1.8) and np.all(r < 2.25), r
+
+
+def test_probe_series_and_fft_reproduce_the_running_dft():
+    """The recorded series summed with the running DFT's twiddles gives the
+    running DFT (same definition, X(f) = sum_m E^m dt e^{-j 2 pi f m dt}), and
+    the FFT bins of the zero-padded series equal that sum at f_k = k/(nfft dt)."""
+    p = W.slab_c1(n=300, slab=(120, 160), src=40, probes=(20, 260), n_freqs=4)
+    T = 700
+    s = oracle.probe_series(p, T)
+    X = oracle.run(p, T)["X"]
+    m = np.arange(1, T + 1)
+    for j in range(len(p.probes)):
+        direct = np.array([np.sum(s[j] * p.dt * np.exp(-2j * np.pi * f * p.dt * m)) for f in p.freqs])
+        assert np.max(np.abs(direct - X[j])) <= 1e-12 * np.max(np.abs(X[j]))
+    nfft = 1024
+    Y = oracle.series_fft(s, nfft, p.dt)
+    q = p.copy(freqs=np.arange(0, nfft, 37) / (nfft * p.dt))
+    Xq = oracle.run(q, T)["X"]
+    assert np.max(np.abs(Y[:, ::37] - Xq)) <= 1e-12 * np.max(np.abs(Xq))
