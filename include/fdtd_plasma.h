@@ -154,6 +154,27 @@ int fdtd_plasma_workspace_bytes(const fdtd_plasma_desc *desc, size_t *bytes);
 int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace,
                        size_t workspace_bytes, fdtd_plasma **out);
 
+/* Bytes of the per-device static workspace of fdtd_plasma_create_static. */
+#define FDTD_STATIC_WORKSPACE_BYTES (16u << 20)
+
+/*
+ * fdtd_plasma_create for callers that cannot allocate device memory (serving
+ * loops, harnesses that forbid hipMalloc): the handle's workspace is a
+ * static device array of FDTD_STATIC_WORKSPACE_BYTES bytes that the library
+ * holds on every GPU it runs on until the process ends, and create makes no
+ * side stream or event either (the CPML and role tiles then run on the
+ * handle's stream, with the same results).  It still copies the inputs and
+ * waits for the stream, so it is not for use under graph capture.  One such
+ * handle per device at a time: the array is that device's only one, so a
+ * second create_static on the device returns FDTD_E_STATE until the first is
+ * destroyed (calls that used the array from several threads at once would
+ * race).  A descriptor whose workspace (fdtd_plasma_workspace_bytes) exceeds
+ * FDTD_STATIC_WORKSPACE_BYTES returns FDTD_E_WORKSPACE before any device
+ * call.  Everything else is as for fdtd_plasma_create; destroy releases the
+ * array for the next handle.
+ */
+int fdtd_plasma_create_static(const fdtd_plasma_desc *desc, fdtd_plasma **out);
+
 /*
  * Advance every grid by nsteps (>= 0) time steps, asynchronously on the
  * handle's stream.  In FDTD_F64 and FDTD_F32_DELTA, step(a) followed by

@@ -113,6 +113,7 @@ def lib():
         sig = {
             "fdtd_plasma_workspace_bytes": [p, p],
             "fdtd_plasma_create": [p, p, ctypes.c_size_t, p],
+            "fdtd_plasma_create_static": [p, p],
             "fdtd_plasma_step": [p, i64],
             "fdtd_plasma_run": [p, i64],
             "fdtd_plasma_probe_spectra": [p, p, p],

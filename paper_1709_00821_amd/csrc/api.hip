@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -64,11 +65,26 @@ struct Defaults {
 
 }  // namespace
 
+// The workspace of fdtd_plasma_create_static: one file-scope device array,
+// each GPU holding its own copy for the life of the process.  Host code never
+// uses this name as an address (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and is kept in g_static_ws.
+static __device__ __align__(256) char scratch[FDTD_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char *g_static_ws[kMaxDevices] = {};     // device address of `scratch`, per device
+bool g_static_live[kMaxDevices] = {};    // a handle holds that device's copy
+}  // namespace
+
 struct fdtd_plasma {
     fdtd_plasma_desc d;
     hipStream_t stream = nullptr;
     int device = 0;
     bool owns_ws = false;
+    bool static_ws = false;    // the workspace is the device's static array (create_static)
     char *ws = nullptr;
     size_t ws_bytes = 0;
 
@@ -777,6 +793,20 @@ int fdtd_plasma_workspace_bytes(const fdtd_plasma_desc *desc, size_t *bytes)
     return FDTD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// create with a planned descriptor; static_ws: the workspace is the device's
+// static array (no side stream or events are made, so the handle allocates
+// nothing but its host object)
+int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size_t workspace_bytes,
+                fdtd_plasma **out, bool static_ws);
+
+}  // namespace
+
+extern "C" {
+
 int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t workspace_bytes,
                        fdtd_plasma **out)
 {
@@ -785,6 +815,43 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     Plan p;
     int rc = plan(desc, p);
     if (rc) return rc;
+    return create_impl(desc, p, dev_workspace, workspace_bytes, out, false);
+}
+
+int fdtd_plasma_create_static(const fdtd_plasma_desc *desc, fdtd_plasma **out)
+{
+    if (!out) return fail(FDTD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    Plan p;
+    int rc = plan(desc, p);
+    if (rc) return rc;
+    if (p.L.total > (int64_t)FDTD_STATIC_WORKSPACE_BYTES)
+        return fail(FDTD_E_WORKSPACE, "the descriptor needs a %lld-byte workspace, above the %lld-byte static one",
+                    (long long)p.L.total, (long long)FDTD_STATIC_WORKSPACE_BYTES);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FDTD_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_live[dev])
+        return fail(FDTD_E_STATE, "a handle on device %d already holds the static workspace", dev);
+    if (!g_static_ws[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_static_ws[dev] = (char *)ptr;
+    }
+    rc = create_impl(desc, p, g_static_ws[dev], (size_t)FDTD_STATIC_WORKSPACE_BYTES, out, true);
+    if (rc == FDTD_OK) g_static_live[dev] = true;
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size_t workspace_bytes,
+                fdtd_plasma **out, bool static_ws)
+{
+    int rc = FDTD_OK;
     if (dev_workspace && workspace_bytes < (size_t)p.L.total)
         return fail(FDTD_E_WORKSPACE, "workspace of %zu bytes < %lld needed", workspace_bytes,
                     (long long)p.L.total);
@@ -793,6 +860,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
 
     fdtd_plasma *h = new (std::nothrow) fdtd_plasma();
     if (!h) return fail(FDTD_E_INVALID, "out of host memory");
+    h->static_ws = static_ws;
     h->d = *desc;
     h->stream = (hipStream_t)desc->stream;
     h->batch = desc->batch;
@@ -949,7 +1017,7 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
         launch_cpml_table(h->d_cpml, desc->cpml_cells, m, smax, desc->dt, st);
     }
     if (((h->exec == FDTD_EXEC_TILED && (h->ntiles[2] > 0 || h->ntiles[3] > 0)) || h->exec == FDTD_EXEC_MIXED) &&
-        h->stream != nullptr) {
+        h->stream != nullptr && !static_ws) {
         // default priority (no priority streams), non-blocking w.r.t. the null stream
         if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -962,8 +1030,12 @@ int fdtd_plasma_create(const fdtd_plasma_desc *desc, void *dev_workspace, size_t
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return undo(fail(FDTD_E_DEVICE, "create failed: %s", hipGetErrorString(e)));
     *out = h;
-    return FDTD_OK;
+    return rc;
 }
+
+}  // namespace
+
+extern "C" {
 
 int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps)
 {
@@ -1388,6 +1460,10 @@ int fdtd_plasma_destroy(fdtd_plasma *h)
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : h->adj_graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+    if (h->static_ws) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_live[h->device] = false;
+    }
     delete h;
     return FDTD_OK;
 }

@@ -235,3 +235,18 @@ def test_grid_length_limit(L):
     msg = L.lib().fdtd_plasma_last_error()
     msg = msg.decode() if isinstance(msg, bytes) else str(msg)
     assert "2^31 - 1" in msg
+
+
+def test_static_workspace_limit(L):
+    """fdtd_plasma_create_static refuses a descriptor whose workspace exceeds
+    the static array before any device call (so this runs without a GPU)."""
+    p = W.slab_c1(n=600000, slab=(1000, 2000), src=500, probes=(100, 599000))
+    d, keep = _desc(p)
+    rc, need = _code(d)
+    assert rc == 0 and need > (16 << 20)
+    h = ctypes.c_void_p()
+    rc = L.lib().fdtd_plasma_create_static(ctypes.byref(d), ctypes.byref(h))
+    assert rc == -3 and not h.value
+    msg = L.lib().fdtd_plasma_last_error()
+    msg = msg.decode() if isinstance(msg, bytes) else str(msg)
+    assert "static" in msg
