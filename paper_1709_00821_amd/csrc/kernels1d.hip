@@ -209,31 +209,47 @@ __global__ void k_dft_twiddle(const double *freqs, int F, int64_t m_first, int c
     tw[t] = make_double2(re, im);
 }
 
-// X[row][f] += sum_i samp[row][i] tw[i][f], summed in a fixed order: lanes of a
-// wave take interleaved sample blocks, then a fixed xor-shuffle tree.
-// One wave per (row, f); SPLIT lanes per output.
-__global__ __launch_bounds__(256) void k_dft_accum(const double *samp, int SB, int64_t rows, int F,
-                                                   int count, const double2 *tw, double2 *X)
+// X[row][f] += sum_i samp[row][i] tw[i][f] over the window's samples, each
+// sum in sample order (deterministic: step(a) + step(b) folds the same
+// windows as step(a + b)).  A 1024-thread workgroup takes kDftRows rows and a
+// group of 64 frequencies: the twiddles of kDftSamp samples at a time are
+// staged in LDS once for all its rows, wave w owns row w of the block, lane l
+// frequency l of the group (coalesced twiddle reads, the sample a scalar load
+// shared by the wave).
+constexpr int kDftRows = 16, kDftSamp = 64;
+
+__global__ __launch_bounds__(1024) void k_dft_accum(const double *samp, int SB, int64_t rows, int F, int count,
+                                                    const double2 *tw, double2 *X)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    __shared__ double2 ltw[kDftSamp][64];
     const int lane = threadIdx.x & 63;
-    if (wave >= rows * F) return;
-    const int64_t row = wave / F;
-    const int f = (int)(wave % F);
-    const double *sp = samp + row * SB;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ngroups = (F + 63) / 64;
+    const int64_t rb = blockIdx.x / ngroups;
+    const int fg = blockIdx.x % ngroups;
+    const int64_t row = rb * kDftRows + w;
+    const int f = fg * 64 + lane;
+    const bool active = row < rows && f < F;
+    const double *sp = samp + (row < rows ? row : 0) * (int64_t)SB;
     double ar = 0.0, ai = 0.0;
-    for (int i = lane; i < count; i += 64) {
-        const double v = sp[i];
-        const double2 w = tw[(int64_t)i * F + f];
-        ar = fmat(v, w.x, ar);
-        ai = fmat(v, w.y, ai);
+    for (int c0 = 0; c0 < count; c0 += kDftSamp) {
+        const int cn = count - c0 < kDftSamp ? count - c0 : kDftSamp;
+        __syncthreads();   // the previous chunk's reads are done
+        for (int e = threadIdx.x; e < cn * 64; e += 1024) {
+            const int i = e >> 6, ff = fg * 64 + (e & 63);
+            ltw[i][e & 63] = ff < F ? tw[(int64_t)(c0 + i) * F + ff] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (row < rows) {
+            for (int i = 0; i < cn; ++i) {
+                const double v = sp[c0 + i];
+                const double2 t = ltw[i][lane];
+                ar = fmat(v, t.x, ar);
+                ai = fmat(v, t.y, ai);
+            }
+        }
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        ar += __shfl_xor(ar, d, 64);
-        ai += __shfl_xor(ai, d, 64);
-    }
-    if (lane == 0) {
+    if (active) {
         double2 x = X[row * F + f];
         x.x += ar;
         x.y += ai;
@@ -245,14 +261,14 @@ void launch_dft(const Grids &g, const double *freqs, int F, int64_t m_first, int
                 double2 *tw, double2 *X, int64_t rows, hipStream_t st)
 {
     // twiddles for at most kTwiddleChunk samples at a time
+    const int64_t blocks = (rows + kDftRows - 1) / kDftRows * ((F + 63) / 64);
     for (int c0 = 0; c0 < count; c0 += kTwiddleChunk) {
         const int cnt = count - c0 < kTwiddleChunk ? count - c0 : kTwiddleChunk;
         const int64_t tot = (int64_t)cnt * F;
         hipLaunchKernelGGL(k_dft_twiddle, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                            freqs, F, m_first + c0, cnt, g.dt, tw);
-        const int64_t waves = rows * F;
-        hipLaunchKernelGGL(k_dft_accum, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st,
-                           (const double *)(g.samp + c0), g.SB, rows, F, cnt, (const double2 *)tw, X);
+        hipLaunchKernelGGL(k_dft_accum, dim3((unsigned)blocks), dim3(1024), 0, st, (const double *)(g.samp + c0),
+                           g.SB, rows, F, cnt, (const double2 *)tw, X);
     }
 }
 

@@ -611,6 +611,14 @@ __device__ __forceinline__ void run_role_any(Chunk<T, C, PLASMA, CPML, JF> &ck, 
                    (r.right_lane >= 0 ? kRoleRight : 0);
 #define FDTDP_ROLE(M) \
     run_role<T, C, PLASMA, CPML, M>(ck, g, r, wp, lane, b, wave_lo, plo, phi, nsteps, slot0, er, hl, post)
+    if constexpr (CPML) {
+        // tiles of a CPML class carry the psi registers too: one variant (the
+        // full role step, whose parts are no-ops where the wave lacks the
+        // node); with two or more, the 512-node instantiations spill
+        (void)rm;
+        FDTDP_ROLE(kRoleAll);
+        return;
+    }
     switch (rm) {
     case 0: FDTDP_ROLE(kRoleProbe); break;
     case kRoleSrc: FDTDP_ROLE(kRoleSrc | kRoleProbe); break;
