@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["rketd1d.c", "adjoint1d.c", "rketd3d.c"]
+_SRCS = ["rketd1d.c", "adjoint1d.c", "rketd3d.c", "rketd2d.c"]
 _lib = None
 # timing builds of the same sources (the benchmark's CPU-baseline leg only):
 # "native" is the serial oracle with -O3 -march=native, "omp" adds -fopenmp
@@ -102,6 +102,8 @@ def _declare(L):
     L.or1d_step.argtypes = [p, p, i64]
     L.or3d_check.argtypes = [p]
     L.or3d_step.argtypes = [p, p, i64]
+    L.or2d_check.argtypes = [p]
+    L.or2d_step.argtypes = [p, p, i64]
     if hasattr(L, "or1d_adjoint_r2"):
         L.or1d_adjoint_r2.argtypes = [p, i64, ctypes.c_int32, p, p, p, p, p]
         L.or1d_adjoint_step.argtypes = [p, p, p, p]
@@ -346,6 +348,81 @@ def run3d(p, nsteps: int, state: Optional[dict] = None, kind: Optional[str] = No
     rc = lib(kind).or3d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
     if rc != 0:
         raise ValueError(f"3D oracle rejected the problem (code {rc})")
+    st["X"] = Xre + 1j * Xim
+    st["step"] = cs.step
+    return st
+
+
+# ---------------------------------------------------------------------------
+# 2D (rketd2d.c)
+# ---------------------------------------------------------------------------
+
+class _Problem2(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+        ("d", ctypes.c_double), ("dt", ctypes.c_double),
+        ("wp2", ctypes.c_void_p * 2), ("nu", ctypes.c_void_p * 2),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("has_src", ctypes.c_int32), ("src_i", ctypes.c_int64), ("src_j", ctypes.c_int64),
+        ("src_tau", ctypes.c_double), ("src_t0", ctypes.c_double), ("src_amp", ctypes.c_double),
+        ("n_probes", ctypes.c_int32), ("n_freqs", ctypes.c_int32),
+        ("probes", ctypes.c_void_p), ("freqs", ctypes.c_void_p),
+    ]
+
+
+class _State2(ctypes.Structure):
+    _fields_ = [
+        ("E", ctypes.c_void_p * 2), ("H", ctypes.c_void_p * 2), ("J", ctypes.c_void_p * 2),
+        ("Xre", ctypes.c_void_p), ("Xim", ctypes.c_void_p), ("step", ctypes.c_int64),
+    ]
+
+
+def _problem2(p, keep: _Keep) -> _Problem2:
+    nc = 1 if p.mode == "tm" else 2
+    wp2 = [keep.arr(p.wp2[c], np.float64) for c in range(nc)]
+    nu = [keep.arr(p.nu[c], np.float64) for c in range(nc)]
+    while len(wp2) < 2:
+        wp2.append(wp2[0])
+        nu.append(nu[0])
+    pr = keep.arr(np.asarray(p.probes, np.int64).reshape(-1, 3), np.int64)
+    fr = keep.arr(p.freqs, np.float64)
+    src = p.src if p.src is not None else (0, 0)
+    return _Problem2(
+        mode=0 if p.mode == "tm" else 1, nx=p.nx, ny=p.ny, d=p.d, dt=p.dt,
+        wp2=(ctypes.c_void_p * 2)(*[_ptr(a) for a in wp2]), nu=(ctypes.c_void_p * 2)(*[_ptr(a) for a in nu]),
+        periodic_x=int(p.periodic_x), periodic_y=int(p.periodic_y), has_src=int(p.src is not None),
+        src_i=int(src[0]), src_j=int(src[1]), src_tau=p.src_tau, src_t0=p.src_t0, src_amp=p.src_amp,
+        n_probes=len(pr), n_freqs=len(fr), probes=_ptr(pr), freqs=_ptr(fr))
+
+
+def new_state2(p) -> dict:
+    nc = 1 if p.mode == "tm" else 2
+    nh = 2 if p.mode == "tm" else 1
+    return {"E": np.zeros((nc, p.nx, p.ny)), "H": np.zeros((nh, p.nx, p.ny)), "J": np.zeros((nc, p.nx, p.ny)),
+            "X": np.zeros((len(p.probes), len(p.freqs)), np.complex128), "step": 0}
+
+
+def check2(p) -> int:
+    keep = _Keep()
+    return lib().or2d_check(ctypes.byref(_problem2(p, keep)))
+
+
+def run2d(p, nsteps: int, state: Optional[dict] = None, kind: Optional[str] = None) -> dict:
+    """Advance a 2D state (default: zero at step 0) by nsteps; returns a new dict
+    with E [ncomp, nx, ny], H [2 (TM: Hx, Hy) or 1 (TE: Hz), nx, ny], J, X."""
+    st = new_state2(p) if state is None else {k: (v.copy() if isinstance(v, np.ndarray) else v)
+                                             for k, v in state.items()}
+    keep = _Keep()
+    pb = _problem2(p, keep)
+    for k in ("E", "H", "J"):
+        st[k] = np.ascontiguousarray(st[k], np.float64)
+    Xre = np.ascontiguousarray(st["X"].real)
+    Xim = np.ascontiguousarray(st["X"].imag)
+    two = lambda a: (ctypes.c_void_p * 2)(*[a[min(c, a.shape[0] - 1)].ctypes.data for c in range(2)])
+    cs = _State2(E=two(st["E"]), H=two(st["H"]), J=two(st["J"]), Xre=_ptr(Xre), Xim=_ptr(Xim), step=st["step"])
+    rc = lib(kind).or2d_step(ctypes.byref(pb), ctypes.byref(cs), nsteps)
+    if rc != 0:
+        raise ValueError(f"2D oracle rejected the problem (code {rc})")
     st["X"] = Xre + 1j * Xim
     st["step"] = cs.step
     return st

@@ -86,6 +86,32 @@ typedef struct {
 int or3d_check(const or3d_problem *pb);
 int or3d_step(const or3d_problem *pb, or3d_state *st, int64_t nsteps);
 
+/* ---- 2D (see rketd2d.c) ---- */
+typedef struct {
+    int32_t mode;              /* 0 TM (Ez, Hx, Hy), 1 TE (Ex, Ey, Hz) */
+    int64_t nx, ny;            /* cells per axis */
+    double d, dt;              /* square cell side (m), time step (s) */
+    const double *wp2[2];      /* [nx*ny] per E component of the mode (TM: [0] only) */
+    const double *nu[2];
+    int32_t periodic_x, periodic_y;
+    int32_t has_src;           /* soft point source on Ez (TM) or Ey (TE) */
+    int64_t src_i, src_j;
+    double src_tau, src_t0, src_amp;
+    int32_t n_probes, n_freqs;
+    const int64_t *probes;     /* [n_probes][3]: E component of the mode, i, j */
+    const double *freqs;       /* Hz */
+} or2d_problem;
+
+typedef struct {
+    double *E[2], *H[2], *J[2];   /* TM: E[0] Ez, H[0] Hx, H[1] Hy, J[0] Jz;
+                                     TE: E[0] Ex, E[1] Ey, H[0] Hz, J[0] Jx, J[1] Jy; [nx*ny] */
+    double *Xre, *Xim;            /* [n_probes][n_freqs] */
+    int64_t step;
+} or2d_state;
+
+int or2d_check(const or2d_problem *pb);
+int or2d_step(const or2d_problem *pb, or2d_state *st, int64_t nsteps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -358,3 +358,117 @@ def sphere_c3(n: int = 384, steps: int = 2000, d: float = 0.5e-3, courant: float
     return Problem3D(nx=n, ny=n, nz=n, d=d, dt=dt, wp2=wp2, nu=nu, src_tau=tau,
                      src_t0=t0, src_amp=amp, freqs=freqs, points=pts, cpml=cpml,
                      source="tfsf", b0=int(tf[0]), b1=int(tf[1]), steps=steps)
+
+
+# ---------------------------------------------------------------------------
+# 2D problems (square cells in the x-y plane, fields uniform along z; arrays
+# [i][j] with j fastest)
+# ---------------------------------------------------------------------------
+
+# E-like components of each 2D mode (each carries its own plasma current)
+MODES_2D = {"tm": ("Ez",), "te": ("Ex", "Ey")}
+# half-cell offsets (x, y) of each 2D component's position
+STAGGER_2D = {"Ez": (0.0, 0.0), "Hx": (0.0, 0.5), "Hy": (0.5, 0.0),
+              "Ex": (0.5, 0.0), "Ey": (0.0, 0.5), "Hz": (0.5, 0.5)}
+
+
+@dataclasses.dataclass
+class Problem2D:
+    """One 2D grid of nx x ny square cells of side d.  TM: Ez at (i, j), Hx at
+    (i, j+1/2), Hy at (i+1/2, j).  TE: Ex at (i+1/2, j), Ey at (i, j+1/2), Hz at
+    (i+1/2, j+1/2).  wp2, nu: [ncomp, nx, ny] at each E component's position."""
+
+    mode: str                         # "tm" | "te"
+    nx: int
+    ny: int
+    d: float
+    dt: float
+    wp2: np.ndarray
+    nu: np.ndarray
+    src: tuple                        # (i, j) of the soft point source (Ez / Ey), or None
+    src_tau: float
+    src_t0: float
+    src_amp: float
+    probes: np.ndarray                # int64 [n, 3]: E component index, i, j
+    freqs: np.ndarray
+    periodic_x: bool = False
+    periodic_y: bool = False
+    steps: int = 0
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def ncomp(self) -> int:
+        return len(MODES_2D[self.mode])
+
+    def vacuum(self) -> "Problem2D":
+        return dataclasses.replace(self, wp2=np.zeros_like(self.wp2))
+
+    def copy(self, **kw) -> "Problem2D":
+        return dataclasses.replace(self, **kw)
+
+
+def cylinder_wp2(mode: str, nx: int, ny: int, centre, radius: float, wp2_peak: float,
+                 edge: float = 0.0) -> np.ndarray:
+    """Plasma cylinder along z: wp^2 = peak inside radius (cells), a Gaussian
+    falloff exp(-((r - radius)/edge)^2) outside it out to radius + 3 edge,
+    sampled at each E component's own position; [ncomp, nx, ny]."""
+    comps = MODES_2D[mode]
+    out = np.zeros((len(comps), nx, ny))
+    for c, name in enumerate(comps):
+        ox, oy = STAGGER_2D[name]
+        x = np.arange(nx) + ox - centre[0]
+        y = np.arange(ny) + oy - centre[1]
+        r = np.sqrt(x[:, None] ** 2 + y[None, :] ** 2)
+        v = np.where(r <= radius, wp2_peak, 0.0)
+        if edge > 0:
+            fall = wp2_peak * np.exp(-((r - radius) / edge) ** 2)
+            v = np.where((r > radius) & (r <= radius + 3 * edge), fall, v)
+        out[c] = v
+    return out
+
+
+def cylinder_2d(mode: str = "tm", n: int = 4096, steps: int = 2000, d: float = 75e-6,
+                courant: float = 0.5, n_freqs: int = 64, seed: int = 1714) -> Problem2D:
+    """n x n cells of d = 75 um (Courant c dt/d = 0.5), PEC walls; a plasma
+    cylinder of radius n/8 at the centre (wp = 2 pi 40 GHz, Gaussian edge of
+    n/64 cells, nu = 20 GHz); the eq.(15) pulse as a soft point source a
+    quarter of the way in; 8 seeded probes on the far half; 64 frequencies
+    over 1-100 GHz."""
+    rng = np.random.default_rng(seed)
+    dt = courant * d / C0
+    tau, t0, amp = pulse_params(dt)
+    wp2 = cylinder_wp2(mode, n, n, (n / 2.0, n / 2.0), n / 8.0, (2 * math.pi * 40 * GHZ) ** 2, n / 64.0)
+    nu = np.full((len(MODES_2D[mode]), n, n), 2e10)
+    comp = 0 if mode == "tm" else 1
+    pi = rng.integers(n // 2, n - 2, 8)
+    pj = rng.integers(2, n - 2, 8)
+    probes = np.stack([np.full(8, comp), pi, pj], axis=1).astype(np.int64)
+    return Problem2D(mode=mode, nx=n, ny=n, d=d, dt=dt, wp2=wp2, nu=nu, src=(n // 4, n // 2),
+                     src_tau=tau, src_t0=t0, src_amp=amp, probes=probes,
+                     freqs=np.linspace(1 * GHZ, 100 * GHZ, n_freqs), steps=steps)
+
+
+def random_2d(rng: np.random.Generator, mode: str, nx: int, ny: int, *, periodic_x: bool = False,
+              periodic_y: bool = False, n_freqs: int = 6, courant: float = 0.5, d: float = 75e-6,
+              plasma: bool = True) -> Problem2D:
+    """A small random 2D problem for parity tests: a random rectangle of
+    per-cell random wp^2 and nu, random source and E probes."""
+    dt = courant * d / C0
+    tau, t0, amp = pulse_params(dt)
+    nc = len(MODES_2D[mode])
+    wp2 = np.zeros((nc, nx, ny))
+    if plasma:
+        i0, i1 = sorted(rng.integers(1, nx, 2))
+        j0, j1 = sorted(rng.integers(1, ny, 2))
+        wp2[:, i0:i1 + 1, j0:j1 + 1] = rng.uniform(0, (2 * math.pi * 40 * GHZ) ** 2, (nc, i1 - i0 + 1, j1 - j0 + 1))
+    nu = rng.uniform(1 * GHZ, 50 * GHZ, (nc, nx, ny))
+    src = (int(rng.integers(1, nx - 1)), int(rng.integers(1, ny - 1)))
+    probes = np.stack([rng.integers(0, nc, 4), rng.integers(1, nx - 1, 4), rng.integers(1, ny - 1, 4)],
+                      axis=1).astype(np.int64)
+    return Problem2D(mode=mode, nx=nx, ny=ny, d=d, dt=dt, wp2=wp2, nu=nu, src=src, src_tau=tau,
+                     src_t0=t0, src_amp=amp, probes=probes,
+                     freqs=np.sort(rng.uniform(1 * GHZ, 100 * GHZ, n_freqs)),
+                     periodic_x=periodic_x, periodic_y=periodic_y)
