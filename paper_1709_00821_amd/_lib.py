@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd_plasma.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fdtd_plasma.h")
 HEADER3 = os.path.join(os.path.dirname(HERE), "include", "fdtd_plasma3d.h")
+HEADER2 = os.path.join(os.path.dirname(HERE), "include", "fdtd_plasma2d.h")
 
 # status codes and enums (include/fdtd_plasma.h)
 OK, E_INVALID, E_UNSTABLE, E_WORKSPACE, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPPORTED = \
@@ -98,6 +99,35 @@ SRC3 = {"none": 0, "planar": 1, "tfsf": 2}
 EXEC3 = {"auto": 0, "split": 1, "fused": 2}
 FIELDS3 = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz", "Jx", "Jy", "Jz")
 
+class Desc2(ctypes.Structure):
+    """fdtd2d_desc (include/fdtd_plasma2d.h)."""
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("mode", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("periodic_x", ctypes.c_int32),
+        ("periodic_y", ctypes.c_int32),
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("d", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("wp2", ctypes.c_void_p),
+        ("nu", ctypes.c_void_p),
+        ("has_src", ctypes.c_int32),
+        ("n_probes", ctypes.c_int32),
+        ("src_i", ctypes.c_int64),
+        ("src_j", ctypes.c_int64),
+        ("src_tau", ctypes.c_double),
+        ("src_t0", ctypes.c_double),
+        ("src_amp", ctypes.c_double),
+        ("n_freqs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("probes", ctypes.c_void_p),
+        ("freqs_hz", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -136,6 +166,14 @@ def lib():
             "fdtd3d_profile": [p, i32],
             "fdtd3d_profile_read": [p, i32, p, p, p, p, p],
             "fdtd3d_destroy": [p],
+            "fdtd2d_workspace_bytes": [p, p],
+            "fdtd2d_create": [p, p, ctypes.c_size_t, p],
+            "fdtd2d_step": [p, i64],
+            "fdtd2d_run": [p, i64],
+            "fdtd2d_spectra": [p, p, p],
+            "fdtd2d_get_fields": [p, i32, p],
+            "fdtd2d_steps_done": [p, p],
+            "fdtd2d_destroy": [p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -145,6 +183,8 @@ def lib():
         L.fdtd_plasma_last_error.restype = ctypes.c_char_p
         L.fdtd3d_last_error.argtypes = []
         L.fdtd3d_last_error.restype = ctypes.c_char_p
+        L.fdtd2d_last_error.argtypes = []
+        L.fdtd2d_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -163,7 +203,14 @@ def check3(rc: int):
     return rc
 
 
+def check2(rc: int):
+    if rc != OK:
+        msg = lib().fdtd2d_last_error().decode(errors="replace")
+        raise FdtdError(rc, msg)
+    return rc
+
+
 def header_symbols(path: str = HEADER):
     """Function names a public header declares."""
     txt = open(path).read()
-    return sorted(set(re.findall(r"\b(fdtd(?:_plasma|3d)_[a-z0-9_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(fdtd(?:_plasma|3d|2d)_[a-z0-9_]+)\s*\(", txt)))

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd_plasma.so")
 SOURCES = ["api.hip", "kernels1d.hip", "blocked1d.hip", "adjoint1d.hip", "fft1d.hip", "api3d.hip",
-           "kernels3d.hip"]
+           "kernels3d.hip", "api2d.hip", "kernels2d.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

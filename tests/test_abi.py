@@ -250,3 +250,19 @@ def test_static_workspace_limit(L):
     msg = L.lib().fdtd_plasma_last_error()
     msg = msg.decode() if isinstance(msg, bytes) else str(msg)
     assert "static" in msg
+
+
+def test_2d_exports_and_validation(L):
+    syms = L.header_symbols(L.HEADER2)
+    assert "fdtd2d_create" in syms and "fdtd2d_run" in syms
+    lib = L.lib()
+    for s in syms:
+        assert hasattr(lib, s)
+    from paper_1709_00821_amd.plasma2d import make_desc2
+    p = W.random_2d(np.random.default_rng(3), "te", 20, 24)
+    for q, code in ((p, 0), (p.copy(dt=0.75 * p.d / 299792458.0), -2),
+                    (p.copy(probes=np.array([[2, 1, 1]])), -1), (p.copy(src=(20, 3)), -1),
+                    (p.copy(wp2=-p.wp2 - 1.0), -1)):
+        d, keep = make_desc2(q)
+        n = ctypes.c_size_t()
+        assert lib.fdtd2d_workspace_bytes(ctypes.byref(d), ctypes.byref(n)) == code

@@ -1,0 +1,108 @@
+"""GPU parity of the 2D Yee-RKETD library (TM and TE) against the 2D oracle
+(through the C ABI): FP64 fields and probe spectra within 1e-12 of the
+oracle's scale, FP32 storage (FP64 registers, rounded every step) within its
+stated error; step composition and graph replay bit for bit."""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_00821_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_00821_amd import plasma2d
+    return plasma2d
+
+
+def rel(a, b, floor=0.0):
+    s = max(float(np.max(np.abs(b))), floor)
+    return float(np.max(np.abs(a - b)) / s) if s > 0 else float(np.max(np.abs(a)))
+
+
+def errs(F, o):
+    # pulse-scale floors: the source peaks at 1 V/m
+    eE = rel(F["E"], o["E"], 1e-2)
+    eH = rel(F["H"], o["H"], 1e-2 / 376.73)
+    eJ = rel(F["J"], o["J"], 1e-6)
+    return eE, eH, eJ
+
+
+@pytest.mark.parametrize("mode,px,py", [("tm", False, False), ("te", False, False), ("tm", True, False),
+                                        ("te", False, True), ("tm", True, True), ("te", True, True)])
+def test_random_2d_matches_oracle(G, mode, px, py):
+    rng = np.random.default_rng(zlib.crc32(f"{mode}{px}{py}".encode()))
+    nx, ny = int(rng.integers(40, 200)), int(rng.integers(40, 200))
+    p = W.random_2d(rng, mode, nx, ny, periodic_x=px, periodic_y=py)
+    T = 400
+    say(f"case 2d {mode} {nx}x{ny} periodic=({px},{py}) steps={T}")
+    o = oracle.run2d(p, T)
+    for prec, tol in (("f64", 1e-12), ("f32", 2e-5)):
+        with G.FdtdPlasma2D(p, precision=prec) as h:
+            h.run(T)
+            X = h.spectra()
+            F = h.fields()
+        ex = rel(X, o["X"])
+        ef = errs(F, o)
+        say(f"2d {mode} {prec}: spectra {ex:.2e} fields E {ef[0]:.2e} H {ef[1]:.2e} J {ef[2]:.2e}")
+        assert ex <= tol and max(ef) <= tol * 10, prec
+    assert np.max(np.abs(o["J"])) > 0
+
+
+@pytest.mark.parametrize("mode", ["tm", "te"])
+def test_cylinder_2d_matches_oracle(G, mode):
+    """The benchmark's plasma-cylinder problem scaled to 192^2 (cylinder radius
+    n/8 with its Gaussian edge, PEC walls, soft point source, 8 probes)."""
+    p = W.cylinder_2d(mode, n=192, n_freqs=16)
+    T = 600
+    say(f"case 2d cylinder {mode} n=192 steps={T}")
+    o = oracle.run2d(p, T)
+    for prec, tol in (("f64", 1e-12), ("f32", 2e-5)):
+        with G.FdtdPlasma2D(p, precision=prec) as h:
+            h.run(T)
+            X = h.spectra()
+            F = h.fields()
+        ex = rel(X, o["X"])
+        ef = errs(F, o)
+        say(f"2d cylinder {mode} {prec}: spectra {ex:.2e} fields {max(ef):.2e}")
+        assert ex <= tol and max(ef) <= tol * 10, prec
+
+
+def test_2d_step_composition_and_replay(G):
+    p = W.random_2d(np.random.default_rng(5), "te", 70, 90)
+    say("case 2d step composition")
+    with G.FdtdPlasma2D(p) as a, G.FdtdPlasma2D(p) as b:
+        a.step(1000).step(0).step(2500)      # crosses a 2048-sample window
+        b.step(3500)
+        assert a.steps_done() == b.steps_done() == 3500
+        assert np.array_equal(a.spectra(), b.spectra())
+        fa, fb = a.fields(), b.fields()
+        for k in ("E", "H", "J"):
+            assert np.array_equal(fa[k], fb[k])
+        b.run(3500)
+        X1 = b.spectra()
+        b.run(3500)
+        assert np.array_equal(b.spectra(), X1) and np.array_equal(X1, a.spectra())
+        for k, v in b.fields().items():
+            assert np.array_equal(v, fa[k])
+
+
+def test_2d_errors(G):
+    from paper_1709_00821_amd import _lib as L
+    p = W.random_2d(np.random.default_rng(6), "tm", 30, 30)
+    with G.FdtdPlasma2D(p) as h:
+        with pytest.raises(L.FdtdError) as e:
+            h.spectra()
+        assert e.value.code == L.E_STATE
