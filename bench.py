@@ -380,6 +380,55 @@ def c3_leg(precision="f32", n=384, T=2000, prof_steps=64, compare_f64=True):
     return out
 
 
+def c2d_leg(n=4096, T=2000, reps=3):
+    """2D Yee-RKETD, TM and TE: n^2 cells, plasma cylinder (radius n/8 with a
+    Gaussian edge), PEC walls, soft point source, 8 probes at 64 frequencies;
+    FP32 storage (FP64 registers), an H pass and an E/J pass per step.
+    Whole-job throughput of run(T) (graph replay), the split passes' effective
+    HBM rate at their algorithmic bytes, and the FP32 spectra against the FP64
+    GPU run of the same problem (the FP64 path is held to the 2D oracle within
+    1e-12 in tests/test_gpu2d.py)."""
+    import torch
+    from paper_1709_00821_amd import workloads as W
+    from paper_1709_00821_amd.plasma2d import FdtdPlasma2D
+    out = {}
+    for mode in ("tm", "te"):
+        p = W.cylinder_2d(mode, n=n, steps=T)
+        N = p.ncells
+        S = int(np.count_nonzero(p.wp2.any(axis=0)))     # cells of the plasma support (at least)
+        res = {}
+        for prec in ("f32", "f64"):
+            with FdtdPlasma2D(p, precision=prec) as h:
+                h.run(T)
+                h.synchronize()
+                ts = []
+                for _ in range(reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(h.stream)
+                    h.run(T)
+                    e1.record(h.stream)
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                res[prec] = (sorted(ts)[len(ts) // 2], h.spectra())
+        ms, X = res["f32"]
+        es = 4
+        nf = 3                                 # field arrays: TM Ez, Hx, Hy; TE Ex, Ey, Hz
+        ncomp = 1 if mode == "tm" else 2
+        # algorithmic bytes per step: every field read and written once; on the
+        # plasma support the currents (FP64) read and written and wp2, nu read
+        alg = N * nf * 2 * es + S * ncomp * (16 + 16)
+        gbs = alg * T / (ms / 1e3) / 1e9
+        err = float(np.max(np.abs(X - res["f64"][1])) / np.max(np.abs(res["f64"][1])))
+        out[mode] = {"value": round(N * T / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s", "ms": round(ms, 2),
+                     "cells": N, "time_steps": T, "precision": "f32", "fp64_ms": round(res["f64"][0], 2),
+                     "plasma_support_cells": S,
+                     "algorithmic_bytes_per_step": int(alg), "effective_gbs": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 3),
+                     "spectra_rel_err_vs_fp64": err}
+        log(f"bench: 2D {mode} {n}^2 x {T}: {ms:.2f} ms ({out[mode]['value']} Mcell/s), fp32 vs fp64 {err:.2e}")
+    return out
+
+
 # the sources the 1D tiled kernels are compiled from (what the counter
 # summary describes); other files of the library do not change them
 TILED_SOURCES = ("physics.h", "internal.h", "tile1d.h", "blocked1d.hip")
@@ -602,7 +651,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=16)
-    ap.add_argument("--only", choices=["c3", "batched", "adjoint", "c1", "table2"],
+    ap.add_argument("--only", choices=["c3", "batched", "adjoint", "c1", "table2", "c2d"],
                     help="run just this leg and print its JSON (profiling runs)")
     ap.add_argument("--c3-steps", type=int, default=2000)
     args = ap.parse_args()
@@ -630,7 +679,7 @@ def main():
         del x, y
     if args.only:
         leg = {"c3": lambda: c3_leg(T=args.c3_steps), "batched": batched_leg, "adjoint": adjoint_leg,
-               "c1": c1_leg, "table2": table2_leg}[args.only]
+               "c1": c1_leg, "table2": table2_leg, "c2d": c2d_leg}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     from paper_1709_00821_amd import workloads as W
@@ -693,6 +742,7 @@ def main():
         out["adjoint"] = adjoint_leg()
         out["c1_latency"] = c1_leg()
         out["c3_3d"] = c3_leg()
+        out["c2d_2d"] = c2d_leg()
         out["paper_table2"] = table2_leg()
     stored = None if args.no_check else stored_oracle_spectra(p, T)
     if stored is not None:

@@ -185,6 +185,49 @@ __device__ __forceinline__ float e_plasma3(float E, float J, float curl, const N
     return fmat(c.eH, curl, fmat(-c.eJ, J, fmat(c.eA, E, E)));
 }
 
+// The corrections of E component C after its update: TF/SF (the total E on
+// a box face reads scattered H outside it, so it gains the incident part
+// Hinc^{n+1/2} times its CH; Ex at k = b0, b1, Ez at i = b0, b1 of a walled
+// x) or the planar source, then PEC (tangential E on the index-0 faces of the
+// walled axes).
+template <int C, typename T>
+__device__ __forceinline__ T e_fix(const Geo3 &g, const double *Hinc, double sval, int64_t i, int64_t j,
+                                   int64_t k, double CH, T e)
+{
+    if (g.src == 2) {
+        if constexpr (C == 0) {
+            if (i >= g.xlo && i < g.xhi && j >= g.ylo && j < g.yhi) {
+                if (k == g.b0) e = e + (T)(CH * Hinc[g.b0 - 1 + g.ao]);
+                else if (k == g.b1) e = e - (T)(CH * Hinc[g.b1 + g.ao]);
+            }
+        }
+        if constexpr (C == 2) {
+            if (!g.px && j >= g.ylo && j < g.yhi && k >= g.b0 && k < g.b1) {
+                if (i == g.b0) e = e - (T)(CH * Hinc[k + g.ao]);
+                else if (i == g.b1) e = e + (T)(CH * Hinc[k + g.ao]);
+            }
+        }
+    } else if (g.src == 1 && k == g.src_k && g.src_comp == C) {
+        e = add_source(e, sval);
+    }
+    const bool wx = !g.px && i == 0, wy = !g.py && j == 0, wz = k == 0;
+    if ((C == 0 && (wy || wz)) || (C == 1 && (wx || wz)) || (C == 2 && (wx || wy))) e = (T)0;
+    return e;
+}
+
+// E component C of a plasma node (compact index cq): its stored
+// coefficients, the E update, the corrections, then J^{n+1} in place.
+template <int C, typename T>
+__device__ __forceinline__ T e_plasma_comp(const Geo3 &g, const Plasma3<T> &pl, const double *Hinc, double sval,
+                                           int64_t i, int64_t j, int64_t k, int64_t cq, T curl, T eo)
+{
+    const NodeCoef<T> cf = coef_at(pl, C, cq);
+    const T J = pl.J[C][cq];
+    const T e = e_fix<C>(g, Hinc, sval, i, j, k, (double)cf.eH, e_plasma3(eo, J, curl, cf));
+    pl.J[C][cq] = (T)j_update<T>((double)J, (double)eo, (double)e, cf);
+    return e;
+}
+
 // E^{n+1} of cell (i, j, k) from its H^{n+1/2} and the H^{n+1/2} of its -1
 // neighbours (zero beyond a wall); e0..e2 hold E^n on entry.  CPML, TF/SF (or
 // the planar source), PEC walls and, on the plasma support, J^{n+1} (written
@@ -231,52 +274,19 @@ __device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, cons
         }
     }
     const T curl0 = dHz_y - dHy_z, curl1 = dHx_z - dHz_x, curl2 = dHy_x - dHx_y;
-    const T eo0 = e0, eo1 = e1, eo2 = e2;
     const int64_t row = i * g.ny + j;
     const int2 sp = pl.span[row];
-    const bool plasma = k >= sp.x && k < sp.y;
-    double CH0 = g.ced, CH2 = g.ced;
-    NodeCoef<T> c0, c1, c2;
-    int64_t cq = 0;
-    if (!plasma) {
+    if (k < sp.x || k >= sp.y) {
         const T ce = (T)g.ced;
-        e0 = fmat(ce, curl0, eo0);
-        e1 = fmat(ce, curl1, eo1);
-        e2 = fmat(ce, curl2, eo2);
+        e0 = e_fix<0>(g, Hinc, sval, i, j, k, g.ced, fmat(ce, curl0, e0));
+        e1 = e_fix<1>(g, Hinc, sval, i, j, k, g.ced, fmat(ce, curl1, e1));
+        e2 = e_fix<2>(g, Hinc, sval, i, j, k, g.ced, fmat(ce, curl2, e2));
     } else {
-        cq = pl.off[row] + (k - sp.x);
-        c0 = coef_at(pl, 0, cq);
-        c1 = coef_at(pl, 1, cq);
-        c2 = coef_at(pl, 2, cq);
-        CH0 = (double)c0.eH;
-        CH2 = (double)c2.eH;
-        e0 = e_plasma3(eo0, pl.J[0][cq], curl0, c0);
-        e1 = e_plasma3(eo1, pl.J[1][cq], curl1, c1);
-        e2 = e_plasma3(eo2, pl.J[2][cq], curl2, c2);
-    }
-    if (g.src == 2) {
-        // total E on a box face reads scattered H outside it: add the incident
-        // part (Hinc^{n+1/2}).  Ex at k = b0, b1; Ez at i = b0, b1 (walled x).
-        if (i >= g.xlo && i < g.xhi && j >= g.ylo && j < g.yhi) {
-            if (k == g.b0) e0 = e0 + (T)(CH0 * Hinc[g.b0 - 1 + g.ao]);
-            else if (k == g.b1) e0 = e0 - (T)(CH0 * Hinc[g.b1 + g.ao]);
-        }
-        if (!g.px && j >= g.ylo && j < g.yhi && k >= g.b0 && k < g.b1) {
-            if (i == g.b0) e2 = e2 - (T)(CH2 * Hinc[k + g.ao]);
-            else if (i == g.b1) e2 = e2 + (T)(CH2 * Hinc[k + g.ao]);
-        }
-    } else if (g.src == 1 && k == g.src_k) {
-        if (g.src_comp == 0) e0 = add_source(e0, sval);
-        else e1 = add_source(e1, sval);
-    }
-    // PEC: tangential E on the index-0 faces of walled axes
-    if (!g.px && i == 0) { e1 = zero; e2 = zero; }
-    if (!g.py && j == 0) { e0 = zero; e2 = zero; }
-    if (k == 0) { e0 = zero; e1 = zero; }
-    if (plasma) {
-        pl.J[0][cq] = (T)j_update<T>((double)pl.J[0][cq], (double)eo0, (double)e0, c0);
-        pl.J[1][cq] = (T)j_update<T>((double)pl.J[1][cq], (double)eo1, (double)e1, c1);
-        pl.J[2][cq] = (T)j_update<T>((double)pl.J[2][cq], (double)eo2, (double)e2, c2);
+        // one component at a time, so that one node's coefficients are live
+        const int64_t cq = pl.off[row] + (k - sp.x);
+        e0 = e_plasma_comp<0>(g, pl, Hinc, sval, i, j, k, cq, curl0, e0);
+        e1 = e_plasma_comp<1>(g, pl, Hinc, sval, i, j, k, cq, curl1, e1);
+        e2 = e_plasma_comp<2>(g, pl, Hinc, sval, i, j, k, cq, curl2, e2);
     }
 }
 

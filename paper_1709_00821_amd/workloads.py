@@ -435,16 +435,18 @@ def cylinder_2d(mode: str = "tm", n: int = 4096, steps: int = 2000, d: float = 7
     """n x n cells of d = 75 um (Courant c dt/d = 0.5), PEC walls; a plasma
     cylinder of radius n/8 at the centre (wp = 2 pi 40 GHz, Gaussian edge of
     n/64 cells, nu = 20 GHz); the eq.(15) pulse as a soft point source a
-    quarter of the way in; 8 seeded probes on the far half; 64 frequencies
-    over 1-100 GHz."""
+    quarter of the way in; 8 probes at seeded angles on a circle of radius
+    n/5 about the source (within the pulse's reach after 2000 steps at
+    n = 4096); 64 frequencies over 1-100 GHz."""
     rng = np.random.default_rng(seed)
     dt = courant * d / C0
     tau, t0, amp = pulse_params(dt)
     wp2 = cylinder_wp2(mode, n, n, (n / 2.0, n / 2.0), n / 8.0, (2 * math.pi * 40 * GHZ) ** 2, n / 64.0)
     nu = np.full((len(MODES_2D[mode]), n, n), 2e10)
     comp = 0 if mode == "tm" else 1
-    pi = rng.integers(n // 2, n - 2, 8)
-    pj = rng.integers(2, n - 2, 8)
+    ang = rng.uniform(0.0, 2 * math.pi, 8)
+    pi = np.clip(np.round(n // 4 + n / 5.0 * np.cos(ang)), 1, n - 2).astype(np.int64)
+    pj = np.clip(np.round(n // 2 + n / 5.0 * np.sin(ang)), 1, n - 2).astype(np.int64)
     probes = np.stack([np.full(8, comp), pi, pj], axis=1).astype(np.int64)
     return Problem2D(mode=mode, nx=n, ny=n, d=d, dt=dt, wp2=wp2, nu=nu, src=(n // 4, n // 2),
                      src_tau=tau, src_t0=t0, src_amp=amp, probes=probes,
