@@ -310,7 +310,7 @@ def c1_leg(reps=5):
             "steps_per_pass": tune["steps_per_pass"]}
 
 
-def c3_leg(precision="f32", n=384, T=2000, prof_steps=64, compare_f64=True):
+def c3_leg(precision="f32", n=384, T=2000, prof_steps=64, compare_f64=True, exec="auto"):
     """3D Yee-RKETD: n^3 cells, plasma sphere in a TF/SF plane wave, CPML,
     FP64 DFT of the tangential E and H on a box in the scattered-field region.
     Whole-job throughput of run(T) (graph replay), plus per-kernel event
@@ -337,7 +337,10 @@ def c3_leg(precision="f32", n=384, T=2000, prof_steps=64, compare_f64=True):
     # auxiliaries read+written per slab cell and axis
     bytes_h = 9 * es * N + 4 * es * slab
     bytes_e = 9 * es * N + S * (6 * es + 3 * 16) + 4 * es * slab
-    with FdtdPlasma3D(p, precision=precision) as h:
+    # the one-pass kernel: E and H read once and written once, both groups of
+    # CPML auxiliaries, the plasma terms of the E pass
+    bytes_f = 12 * es * N + S * (6 * es + 3 * 16) + 8 * es * slab
+    with FdtdPlasma3D(p, precision=precision, exec=exec) as h:
         h.profile(True)
         h.step(prof_steps)
         prof = h.profile_read()
@@ -357,13 +360,13 @@ def c3_leg(precision="f32", n=384, T=2000, prof_steps=64, compare_f64=True):
     for k, (kms, calls, cells) in prof.items():
         kern[k] = {"us_per_launch": round(kms / calls * 1e3, 2), "launches": calls}
     out = {"value": round(N * T / (ms / 1e3) / 1e6, 1), "unit": "Mcell-updates/s",
-           "ms": round(ms, 2), "cells": N, "time_steps": T, "precision": precision,
+           "ms": round(ms, 2), "cells": N, "time_steps": T, "precision": precision, "exec": exec,
            "plasma_support_cells": S, "cpml_slab_cells": slab, "sample_points": npts,
            "freqs": F, "spectra_finite": bool(np.all(np.isfinite(X))), "kernels": kern}
     if precision != "f64" and compare_f64:
         # the same run in FP64 on the GPU: the FP64 path is held to the oracle
         # within 1e-12 on the same problem scaled to 96^3 (tests/test_gpu3d.py)
-        with FdtdPlasma3D(p, precision="f64") as h64:
+        with FdtdPlasma3D(p, precision="f64", exec=exec) as h64:
             h64.run(T)
             X64 = h64.spectra()
         err = np.abs(X - X64)
@@ -371,7 +374,7 @@ def c3_leg(precision="f32", n=384, T=2000, prof_steps=64, compare_f64=True):
                            "reference": "the FP64 GPU run of the same problem (within 1e-12 of the "
                                         "oracle at 96^3)"}
         log(f"bench: 3D fp32 vs fp64 spectra {out['accuracy']['spectra_rel_err_vs_fp64']:.2e}")
-    for k, b in (("k_e3d", bytes_e), ("k_h3d", bytes_h)):
+    for k, b in (("k_e3d", bytes_e), ("k_h3d", bytes_h), ("k_fused3d", bytes_f)):
         if k in prof:
             kms, calls, _ = prof[k]
             gbs = b / (kms / calls / 1e3) / 1e9
@@ -654,6 +657,7 @@ def main():
     ap.add_argument("--only", choices=["c3", "batched", "adjoint", "c1", "table2", "c2d"],
                     help="run just this leg and print its JSON (profiling runs)")
     ap.add_argument("--c3-steps", type=int, default=2000)
+    ap.add_argument("--c3-exec", default="auto", choices=["auto", "split", "fused"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -678,7 +682,7 @@ def main():
         log(f"bench: copy calibration: hipMemcpy of {nbytes} bytes (rc {rc})")
         del x, y
     if args.only:
-        leg = {"c3": lambda: c3_leg(T=args.c3_steps), "batched": batched_leg, "adjoint": adjoint_leg,
+        leg = {"c3": lambda: c3_leg(T=args.c3_steps, exec=args.c3_exec), "batched": batched_leg, "adjoint": adjoint_leg,
                "c1": c1_leg, "table2": table2_leg, "c2d": c2d_leg}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return

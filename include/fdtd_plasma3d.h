@@ -54,9 +54,10 @@ enum { FDTD3D_SRC_NONE = 0, FDTD3D_SRC_PLANAR = 1, FDTD3D_SRC_TFSF = 2 };
 
 /* How a time step is executed (identical bits either way):
  * SPLIT: an H pass and an E/J pass over the grid, fields updated in place;
- * FUSED: one pass (tiles marching along x with E staged in LDS), E, H and the
- *        CPML auxiliaries ping-ponged between two copies.  AUTO = SPLIT (the
- *        faster of the two on MI355X at present). */
+ * FUSED: one pass (waves marching along x, each recomputing the H of its
+ *        j-1 and k-1 rim from E^n), E, H and the CPML auxiliaries ping-ponged
+ *        between two copies.  AUTO = SPLIT (the faster of the two on MI355X
+ *        at present). */
 enum { FDTD3D_EXEC_AUTO = 0, FDTD3D_EXEC_SPLIT = 1, FDTD3D_EXEC_FUSED = 2 };
 
 /* Field selectors of get/set_fields: E, H components, then the currents. */
@@ -89,7 +90,7 @@ typedef struct {
                                 * 0 = 32, else 1..32 */
     int32_t exec;              /* FDTD3D_EXEC_* */
     int32_t x_planes;          /* x-planes each thread of the split kernels walks (1..16,
-                                * default 4), or each fused-kernel workgroup (2..128,
+                                * default 4), or each fused-kernel wave (2..128,
                                 * default 32); 0 = default */
     int32_t reserved;
     void *stream;              /* hipStream_t to launch on (NULL: the legacy null stream,

@@ -221,9 +221,9 @@ int plan3(const fdtd3d_desc *d, Plan3 &pl, bool keep_tables)
         pl.oCA[c] = L.take(S * es);
         pl.oCJ[c] = L.take(S * es);
         pl.oCH[c] = L.take(S * es);
-        pl.oCa[c] = L.take(S * 8);
-        pl.oCb1[c] = L.take(S * 8);
-        pl.oCb2[c] = L.take(S * 8);
+        pl.oCa[c] = L.take(S * es);
+        pl.oCb1[c] = L.take(S * es);
+        pl.oCb2[c] = L.take(S * es);
     }
     pl.oSpan = L.take(pl.rows * 8);
     pl.oOff = L.take(pl.rows * 8);
@@ -321,9 +321,9 @@ Plasma3<T> plasma_of(const fdtd3d *h)
         p.eA[c] = h->at<T>(h->pl.oCA[c]);
         p.eJ[c] = h->at<T>(h->pl.oCJ[c]);
         p.eH[c] = h->at<T>(h->pl.oCH[c]);
-        p.ca[c] = h->at<double>(h->pl.oCa[c]);
-        p.cb1[c] = h->at<double>(h->pl.oCb1[c]);
-        p.cb2[c] = h->at<double>(h->pl.oCb2[c]);
+        p.ca[c] = h->at<T>(h->pl.oCa[c]);
+        p.cb1[c] = h->at<T>(h->pl.oCb1[c]);
+        p.cb2[c] = h->at<T>(h->pl.oCb2[c]);
     }
     return p;
 }
@@ -570,24 +570,25 @@ int fdtd3d_create(const fdtd3d_desc *desc, void *workspace, size_t bytes, fdtd3d
     // coefficient tables of the plasma support (a0), built on the device
     if (e == hipSuccess && pl.S > 0) {
         const double *w[3], *n[3];
-        double *ca[3], *cb1[3], *cb2[3];
-        void *eA[3], *eJ[3], *eH[3];
+        void *eA[3], *eJ[3], *eH[3], *ca[3], *cb1[3], *cb2[3];
         for (int c = 0; c < 3; ++c) {
             w[c] = h->at<double>(pl.oW[c]);
             n[c] = h->at<double>(pl.oNu[c]);
-            ca[c] = h->at<double>(pl.oCa[c]);
-            cb1[c] = h->at<double>(pl.oCb1[c]);
-            cb2[c] = h->at<double>(pl.oCb2[c]);
+            ca[c] = h->ws + pl.oCa[c];
+            cb1[c] = h->ws + pl.oCb1[c];
+            cb2[c] = h->ws + pl.oCb2[c];
             eA[c] = h->ws + pl.oCA[c];
             eJ[c] = h->ws + pl.oCJ[c];
             eH[c] = h->ws + pl.oCH[c];
         }
         if (pl.esize == 8)
             launch_coef3d<double>(w, n, pl.S, d.dt, d.d, (double *const *)eA, (double *const *)eJ,
-                                  (double *const *)eH, ca, cb1, cb2, h->stream);
+                                  (double *const *)eH, (double *const *)ca, (double *const *)cb1,
+                                  (double *const *)cb2, h->stream);
         else
             launch_coef3d<float>(w, n, pl.S, d.dt, d.d, (float *const *)eA, (float *const *)eJ,
-                                 (float *const *)eH, ca, cb1, cb2, h->stream);
+                                 (float *const *)eH, (float *const *)ca, (float *const *)cb1,
+                                 (float *const *)cb2, h->stream);
         e = hipGetLastError();
     }
     // the host pointers of the caller are not kept

@@ -38,23 +38,25 @@ struct Fields3 {
 // Plasma support: per row (i, j) the span [k0, k1) of nodes with a current;
 // the row's nodes are stored compactly from off[row].  The per-node
 // coefficients of each E component are built once per create (k_coef3d)
-// into compact tables: the E-update triple in the storage precision (FP64:
-// CA, CJ, CH; FP32: CA - 1, CJ, CH) and the exponential-integrator triple
-// a, b1, b2 of the J update in FP64.
+// into compact tables in the storage precision: the E-update triple (FP64:
+// CA, CJ, CH; FP32: CA - 1, CJ, CH) and the exponential-integrator triple of
+// the J update (FP64: a, b1, b2; FP32: a - 1, b1, b2, which J, itself stored
+// in FP32, carries to no worse than its own rounding).  The J update runs in
+// FP64 registers on the widened values.
 template <typename T>
 struct Plasma3 {
     const int2 *span;             // [nx*ny] (k0, k1); k0 == k1: no plasma in the row
     const int64_t *off;           // [nx*ny]
     T *J[3];                      // compact [S]
     const T *eA[3], *eJ[3], *eH[3];          // compact [S]
-    const double *ca[3], *cb1[3], *cb2[3];   // compact [S]
+    const T *ca[3], *cb1[3], *cb2[3];        // compact [S]
 };
 
 // Build the compact coefficient tables from wp2, nu (compact, FP64).
 template <typename T>
 void launch_coef3d(const double *const wp2[3], const double *const nu[3], int64_t S, double dt, double d,
-                   T *const eA[3], T *const eJ[3], T *const eH[3], double *const ca[3], double *const cb1[3],
-                   double *const cb2[3], hipStream_t st);
+                   T *const eA[3], T *const eJ[3], T *const eH[3], T *const ca[3], T *const cb1[3],
+                   T *const cb2[3], hipStream_t st);
 
 
 
@@ -76,7 +78,6 @@ struct Cpml3 {
     const T *tab;                 // [3 axes][4: bE, aE, bH, aH][2P]
 };
 
-constexpr int kFusedRows = 4;     // rows (j) of a fused-kernel tile; tiles are 64 (k) x 4 (j)
 
 template <typename T>
 void launch_h3d(const Geo3 &g, const Fields3<T> &f, const Cpml3<T> &c, const double *Einc,

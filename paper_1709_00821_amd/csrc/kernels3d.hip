@@ -143,9 +143,9 @@ __device__ __forceinline__ NodeCoef<T> coef_at(const Plasma3<T> &pl, int c, int6
     r.eA = pl.eA[c][q];
     r.eJ = pl.eJ[c][q];
     r.eH = pl.eH[c][q];
-    r.a = pl.ca[c][q];
-    r.b1 = pl.cb1[c][q];
-    r.b2 = pl.cb2[c][q];
+    r.a = sizeof(T) == 8 ? (double)pl.ca[c][q] : 1.0 + (double)pl.ca[c][q];
+    r.b1 = (double)pl.cb1[c][q];
+    r.b2 = (double)pl.cb2[c][q];
     return r;
 }
 
@@ -154,25 +154,52 @@ __device__ __forceinline__ NodeCoef<T> coef_at(const Plasma3<T> &pl, int c, int6
 template <typename T>
 __global__ void k_coef3d(const double *w0, const double *w1, const double *w2, const double *n0,
                          const double *n1, const double *n2, int64_t S, double dt, double d, T *eA0, T *eA1,
-                         T *eA2, T *eJ0, T *eJ1, T *eJ2, T *eH0, T *eH1, T *eH2, double *a0, double *a1,
-                         double *a2, double *b10, double *b11, double *b12, double *b20, double *b21,
-                         double *b22)
+                         T *eA2, T *eJ0, T *eJ1, T *eJ2, T *eH0, T *eH1, T *eH2, T *a0, T *a1, T *a2,
+                         T *b10, T *b11, T *b12, T *b20, T *b21, T *b22)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= S) return;
     const double *w[3] = {w0, w1, w2}, *n[3] = {n0, n1, n2};
     T *eA[3] = {eA0, eA1, eA2}, *eJ[3] = {eJ0, eJ1, eJ2}, *eH[3] = {eH0, eH1, eH2};
-    double *a[3] = {a0, a1, a2}, *b1[3] = {b10, b11, b12}, *b2[3] = {b20, b21, b22};
+    T *a[3] = {a0, a1, a2}, *b1[3] = {b10, b11, b12}, *b2[3] = {b20, b21, b22};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const NodeCoef<T> r = node_coef_t<T>(w[c][q], n[c][q], dt, d, 0);
         eA[c][q] = r.eA;
         eJ[c][q] = r.eJ;
         eH[c][q] = r.eH;
-        a[c][q] = r.a;
-        b1[c][q] = r.b1;
-        b2[c][q] = r.b2;
+        a[c][q] = sizeof(T) == 8 ? (T)r.a : (T)(r.a - 1.0);   // a in [1/2, 1]: a - 1 exact
+        b1[c][q] = (T)r.b1;
+        b2[c][q] = (T)r.b2;
     }
+}
+
+// The plasma terms of one cell, read before its E update (with its field
+// values, so that no load waits on another): whether the cell is on the
+// support, its compact index, J^n and the stored coefficients of the three
+// components.  sp, off: the span and offset of the cell's row.
+template <typename T>
+struct PNode {
+    bool on;
+    int64_t cq;
+    T J[3];
+    NodeCoef<T> cf[3];
+};
+
+template <typename T>
+__device__ __forceinline__ PNode<T> pnode_load(const Plasma3<T> &pl, int2 sp, int64_t off, int64_t k)
+{
+    PNode<T> n;
+    n.on = k >= sp.x && k < sp.y;
+    n.cq = off + (k - sp.x);
+    if (n.on) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            n.J[c] = pl.J[c][n.cq];
+            n.cf[c] = coef_at(pl, c, n.cq);
+        }
+    }
+    return n;
 }
 
 // E update with the 3D curl sign: E_new = CA E - CJ J + CH curl.
@@ -215,26 +242,27 @@ __device__ __forceinline__ T e_fix(const Geo3 &g, const double *Hinc, double sva
     return e;
 }
 
-// E component C of a plasma node (compact index cq): its stored
-// coefficients, the E update, the corrections, then J^{n+1} in place.
+// E component C of a plasma node: the E update with its coefficients, the
+// corrections, then J^{n+1} in place.
 template <int C, typename T>
-__device__ __forceinline__ T e_plasma_comp(const Geo3 &g, const Plasma3<T> &pl, const double *Hinc, double sval,
-                                           int64_t i, int64_t j, int64_t k, int64_t cq, T curl, T eo)
+__device__ __forceinline__ T e_plasma_comp(const Geo3 &g, const Plasma3<T> &pl, const PNode<T> &pn,
+                                           const double *Hinc, double sval, int64_t i, int64_t j, int64_t k,
+                                           T curl, T eo)
 {
-    const NodeCoef<T> cf = coef_at(pl, C, cq);
-    const T J = pl.J[C][cq];
+    const NodeCoef<T> &cf = pn.cf[C];
+    const T J = pn.J[C];
     const T e = e_fix<C>(g, Hinc, sval, i, j, k, (double)cf.eH, e_plasma3(eo, J, curl, cf));
-    pl.J[C][cq] = (T)j_update<T>((double)J, (double)eo, (double)e, cf);
+    pl.J[C][pn.cq] = (T)j_update<T>((double)J, (double)eo, (double)e, cf);
     return e;
 }
 
 // E^{n+1} of cell (i, j, k) from its H^{n+1/2} and the H^{n+1/2} of its -1
 // neighbours (zero beyond a wall); e0..e2 hold E^n on entry.  CPML, TF/SF (or
-// the planar source), PEC walls and, on the plasma support, J^{n+1} (written
-// in place).  Shared by both executors.
+// the planar source), PEC walls and, on the plasma support (pn, read by the
+// caller), J^{n+1} (written in place).  Shared by both executors.
 template <typename T>
-__device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, const Cpml3<T> &c,
-                                       const double *Hinc, double sval, int64_t i, int64_t j, int64_t k,
+__device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, const PNode<T> &pn,
+                                       const Cpml3<T> &c, const double *Hinc, double sval, int64_t i, int64_t j, int64_t k,
                                        T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
                                        T &e0, T &e1, T &e2)
 {
@@ -274,19 +302,15 @@ __device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, cons
         }
     }
     const T curl0 = dHz_y - dHy_z, curl1 = dHx_z - dHz_x, curl2 = dHy_x - dHx_y;
-    const int64_t row = i * g.ny + j;
-    const int2 sp = pl.span[row];
-    if (k < sp.x || k >= sp.y) {
+    if (!pn.on) {
         const T ce = (T)g.ced;
         e0 = e_fix<0>(g, Hinc, sval, i, j, k, g.ced, fmat(ce, curl0, e0));
         e1 = e_fix<1>(g, Hinc, sval, i, j, k, g.ced, fmat(ce, curl1, e1));
         e2 = e_fix<2>(g, Hinc, sval, i, j, k, g.ced, fmat(ce, curl2, e2));
     } else {
-        // one component at a time, so that one node's coefficients are live
-        const int64_t cq = pl.off[row] + (k - sp.x);
-        e0 = e_plasma_comp<0>(g, pl, Hinc, sval, i, j, k, cq, curl0, e0);
-        e1 = e_plasma_comp<1>(g, pl, Hinc, sval, i, j, k, cq, curl1, e1);
-        e2 = e_plasma_comp<2>(g, pl, Hinc, sval, i, j, k, cq, curl2, e2);
+        e0 = e_plasma_comp<0>(g, pl, pn, Hinc, sval, i, j, k, curl0, e0);
+        e1 = e_plasma_comp<1>(g, pl, pn, Hinc, sval, i, j, k, curl1, e1);
+        e2 = e_plasma_comp<2>(g, pl, pn, Hinc, sval, i, j, k, curl2, e2);
     }
 }
 
@@ -349,126 +373,183 @@ __global__ __launch_bounds__(256) void k_e3d(Geo3 g, Fields3<T> f, Plasma3<T> pl
         hy_i = Hy[pm];
         hz_i = Hz[pm];
     }
-    for (int64_t i = q.i0; i < q.i1; ++i, p += sI) {
+    // the support span of the row, read one plane ahead
+    int64_t row = q.i0 * g.ny + j;
+    int2 sp = pl.span[row];
+    int64_t of = pl.off[row];
+    for (int64_t i = q.i0; i < q.i1; ++i, p += sI, row += g.ny) {
+        int2 spn = sp;
+        int64_t ofn = of;
+        if (i + 1 < q.i1) {
+            spn = pl.span[row + g.ny];
+            ofn = pl.off[row + g.ny];
+        }
         const T hx = Hx[p], hy = Hy[p], hz = Hz[p];
         const T hz_j = Hz[p + dj], hx_j = Hx[p + dj], hy_k = Hy[p + dk], hx_k = Hx[p + dk];
         T e0 = f.E[0][p], e1 = f.E[1][p], e2 = f.E[2][p];
-        e_cell<T>(g, pl, c, Hinc, sval, i, j, k, hx, hy, hz, hasj ? hx_j : zero, hask ? hx_k : zero, hy_i,
+        const PNode<T> pn = pnode_load(pl, sp, of, k);
+        e_cell<T>(g, pl, pn, c, Hinc, sval, i, j, k, hx, hy, hz, hasj ? hx_j : zero, hask ? hx_k : zero, hy_i,
                   hask ? hy_k : zero, hz_i, hasj ? hz_j : zero, e0, e1, e2);
         f.E[0][p] = e0;
         f.E[1][p] = e1;
         f.E[2][p] = e2;
         hy_i = hy;
         hz_i = hz;
+        sp = spn;
+        of = ofn;
     }
 }
 
 // ---- fused step ---------------------------------------------------------------
 //
-// One workgroup owns a 64 (k) x 4 (j) column of cells over a chunk of planes
-// [i0, i1) and marches along i.  Per plane it stages E^n of the tile plus a
-// one-cell rim (rows j0-1 .. j0+4, columns k0-1 .. k0+64) in LDS, computes
-// H^{n+1/2} on the tile plus its low rim (row j0-1, column k0-1, recomputed
-// from E^n exactly as their owners do, written back only by the owner), then
-// E^{n+1} and J^{n+1} of the tile from the H of this plane and the previous
-// one.  The chunk starts one plane early (i0-1) to produce the H its first E
-// plane needs.  E, H and the CPML auxiliaries are read from one copy and
-// written to the other, so no workgroup reads a value another has already
-// advanced.  HBM traffic per cell: E and H read once, written once.
+// One wave owns 63 cells of a row, k0 .. k0+62 of row j, over a chunk of
+// planes [i0, i1), and marches along x; its 64 lanes hold the cells
+// k0-1 .. k0+62.  Per plane every lane computes H^{n+1/2} of its cell and,
+// for the E update of its own cell, the Hx and Hz of the cell at j-1 (both
+// from E^n and H^{n-1/2} read from the input copy, exactly as the owners of
+// those cells compute them); the H at k-1 is the lane below's (a cross-lane
+// move), which is why lane 0 holds the cell k0-1 and updates no E.  Then
+// E^{n+1} and J^{n+1} of cells k0 .. k0+62 from that H and the H of the
+// previous plane, kept in registers; the chunk starts one plane early (i0-1)
+// for the H its first E plane needs.  E, H and the CPML auxiliaries are read
+// from one copy and written to the other, so no wave reads a value another
+// has already advanced and no wave waits on another (no barrier, no LDS).
+// The loads of plane i+1 are issued before the arithmetic of plane i.  HBM
+// traffic per cell: E and H read once and written once; the rim reads (rows
+// j +- 1, the lane-0 column, the lead-in plane) are re-reads that hit L2.
+
+__device__ __forceinline__ float lane_up1(float x)
+{
+    // lane l receives lane l-1's value, lane 0 receives 0 (DPP wave_shr:1)
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF,
+                                                                 false));
+}
+__device__ __forceinline__ double lane_up1(double x)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(0, v.x, 0x138, 0xF, 0xF, false),
+                                                __builtin_amdgcn_update_dpp(0, v.y, 0x138, 0xF, 0xF, false)));
+}
+
+// What one plane of a fused-kernel lane reads from the input copy.
+template <typename T>
+struct Plane3 {
+    T e[3];        // E^n(i, j, k)
+    T eyi, ezi;    // Ey, Ez at (i+1, j, k)
+    T exj, ezj;    // Ex, Ez at (i, j+1, k)
+    T exk, eyk;    // Ex, Ey at (i, j, k+1)
+    T m[3];        // E^n(i, j-1, k)
+    T myk, myi;    // Ey at (i, j-1, k+1) and (i+1, j-1, k)
+    T h[3];        // H^{n-1/2}(i, j, k)
+    T hmx, hmz;    // Hx, Hz at (i, j-1, k)
+};
+
+template <typename T>
+__device__ __forceinline__ T ld_if(const T *a, int64_t p, bool ok)
+{
+    return ok ? a[p] : (T)0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fused3d(Geo3 g, Fields3<T> fin, Fields3<T> fout, Plasma3<T> pl,
                                                  Cpml3<T> c, const double *Einc, const double *Hinc,
                                                  double sval, int ni)
 {
-    constexpr int TJ = kFusedRows, NT = TJ * 64;
-    constexpr int PJ = TJ + 2, PK = 66;        // E patch: rows j0-1 .. j0+TJ, cols k0-1 .. k0+64
-    constexpr int HJ = TJ + 1, HK = 65;        // H patch: rows j0-1 .. j0+TJ-1, cols k0-1 .. k0+63
-    __shared__ T sE[2][3][PJ * PK];
-    __shared__ T sH[2][3][HJ * HK];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t kbf = (g.nz + 62) / 63;
     const int64_t bid = xcd_chunk(blockIdx.x, gridDim.x);
-    const int64_t kq = bid % g.kb, r = bid / g.kb;
-    const int64_t j0 = (r % g.jb) * TJ, i0 = (r / g.jb) * ni, k0 = kq * 64;
+    const int64_t kq = bid % kbf, r = bid / kbf;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t j = (r % g.jb) * 4 + w;
+    if (j >= g.ny) return;                           // the whole wave; no wave waits on another
+    const int64_t i0 = (r / g.jb) * ni;
     const int64_t i1 = i0 + ni < g.nx ? i0 + ni : g.nx;
+    const int64_t k = kq * 63 - 1 + lane;
+    const bool vk = k >= 0 && k < g.nz;             // the lane's cell exists
+    const bool own = vk && lane > 0;                 // and is this wave's
+    const bool hasj = g.py || j + 1 < g.ny;          // row j+1 exists (wrapped if periodic)
+    const bool hasjm = g.py || j > 0;                // row j-1 exists
+    const int64_t jp = j + 1 < g.ny ? j + 1 : 0, jm = j > 0 ? j - 1 : g.ny - 1;
+    const bool hask = k + 1 < g.nz;
     const T zero = (T)0;
 
-    // index along an axis: in range, wrapped (periodic), or absent (wall)
-    auto wrap = [](int64_t x, int64_t n, bool per, bool &ok) -> int64_t {
-        if (x >= 0 && x < n) { ok = true; return x; }
-        ok = per;
-        const int64_t m = x % n;            // in range even where n < the rim
-        return m < 0 ? m + n : m;
-    };
-    auto load_plane = [&](int64_t ip, int buf) {
-        bool iok;
-        const int64_t gi = wrap(ip, g.nx, g.px != 0, iok);
-        for (int e = tid; e < PJ * PK; e += NT) {
-            const int pj = e / PK, pk = e - pj * PK;
-            bool jok;
-            const int64_t gj = wrap(j0 - 1 + pj, g.ny, g.py != 0, jok);
-            const int64_t gk = k0 - 1 + pk;
-            const bool ok = iok && jok && gk >= 0 && gk < g.nz;
-            const int64_t p = ok ? (gi * g.ny + gj) * g.nz + gk : 0;
-            sE[buf][0][e] = ok ? fin.E[0][p] : zero;
-            sE[buf][1][e] = ok ? fin.E[1][p] : zero;
-            sE[buf][2][e] = ok ? fin.E[2][p] : zero;
+    auto load = [&](int64_t gi, Plane3<T> &q) {
+        const bool hasi = g.px || gi + 1 < g.nx;     // plane i+1 exists (wrapped if periodic)
+        const int64_t gi1 = gi + 1 < g.nx ? gi + 1 : 0;
+        const int64_t p = (gi * g.ny + j) * g.nz + k, p1 = (gi1 * g.ny + j) * g.nz + k;
+        const int64_t pj = (gi * g.ny + jp) * g.nz + k, pm = (gi * g.ny + jm) * g.nz + k;
+        const int64_t pm1 = (gi1 * g.ny + jm) * g.nz + k;
+        const bool hm = vk && hasjm;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q.e[a] = ld_if(fin.E[a], p, vk);
+            q.m[a] = ld_if(fin.E[a], pm, hm);
+            q.h[a] = ld_if(fin.H[a], p, vk);
         }
+        q.eyi = ld_if(fin.E[1], p1, vk && hasi);
+        q.ezi = ld_if(fin.E[2], p1, vk && hasi);
+        q.exj = ld_if(fin.E[0], pj, vk && hasj);
+        q.ezj = ld_if(fin.E[2], pj, vk && hasj);
+        q.exk = ld_if(fin.E[0], p + 1, vk && hask);
+        q.eyk = ld_if(fin.E[1], p + 1, vk && hask);
+        q.myk = ld_if(fin.E[1], pm + 1, hm && hask);
+        q.myi = ld_if(fin.E[1], pm1, hm && hasi);
+        q.hmx = ld_if(fin.H[0], pm, hm);
+        q.hmz = ld_if(fin.H[2], pm, hm);
     };
+    auto wrap = [&](int64_t i) { return i < 0 ? i + g.nx : i; };
 
-    load_plane(i0 - 1, (int)((i0 - 1) & 1));
-    for (int64_t i = i0 - 1; i < i1; ++i) {
-        const int eb = (int)(i & 1), en = (int)((i + 1) & 1);
-        load_plane(i + 1, en);
-        __syncthreads();
-        // H^{n+1/2} on the H patch of plane i
-        {
-            bool iok;
-            const int64_t gi = wrap(i, g.nx, g.px != 0, iok);
-            for (int e = tid; e < HJ * HK; e += NT) {
-                const int hj = e / HK, hk = e - hj * HK;
-                bool jok;
-                const int64_t uj = j0 - 1 + hj;
-                const int64_t gj = wrap(uj, g.ny, g.py != 0, jok);
-                const int64_t gk = k0 - 1 + hk;
-                T hx = zero, hy = zero, hz = zero;
-                if (iok && jok && gk >= 0 && gk < g.nz) {
-                    const int64_t p = (gi * g.ny + gj) * g.nz + gk;
-                    const int a = hj * PK + hk;
-                    hx = fin.H[0][p];
-                    hy = fin.H[1][p];
-                    hz = fin.H[2][p];
-                    const bool own = hj >= 1 && hk >= 1 && uj < g.ny && i >= i0;
-                    h_cell<T>(g, c, Einc, gi, gj, gk, sE[eb][0][a], sE[eb][1][a], sE[eb][2][a],
-                              sE[eb][0][a + PK], sE[eb][0][a + 1], sE[en][1][a], sE[eb][1][a + 1],
-                              sE[en][2][a], sE[eb][2][a + PK], hx, hy, hz, own);
-                    if (own) {
-                        fout.H[0][p] = hx;
-                        fout.H[1][p] = hy;
-                        fout.H[2][p] = hz;
-                    }
-                }
-                sH[eb][0][e] = hx;
-                sH[eb][1][e] = hy;
-                sH[eb][2][e] = hz;
+    // the lead-in plane i0-1: wrapped to nx-1 on a periodic x, absent at a wall
+    int64_t i = (i0 > 0 || g.px) ? i0 - 1 : i0;
+    T hy_i = zero, hz_i = zero;                      // H^{n+1/2} of the previous plane
+    Plane3<T> cur, nxt;
+    load(wrap(i), cur);
+    int2 sp = pl.span[i0 * g.ny + j];                // support span of the next E plane's row
+    int64_t of = pl.off[i0 * g.ny + j];
+    for (; i < i1; ++i) {
+        const int64_t gi = wrap(i);
+        const bool lead = i < i0;
+        // this plane's plasma terms first, then the next plane's fields: the
+        // E update waits on neither the next plane's loads nor a chain of its own
+        PNode<T> pn;
+        pn.on = false;
+        int2 spn = sp;
+        int64_t ofn = of;
+        if (!lead) {
+            pn = pnode_load(pl, sp, of, k);
+            if (i + 1 < i1) {
+                spn = pl.span[(i + 1) * g.ny + j];
+                ofn = pl.off[(i + 1) * g.ny + j];
             }
         }
-        __syncthreads();
-        // E^{n+1}, J^{n+1} of the tile in plane i
-        const int64_t j = j0 + w, k = k0 + lane;
-        if (i >= i0 && j < g.ny && k < g.nz) {
-            const int hp = (int)((i - 1) & 1);
-            const int a = (w + 1) * HK + lane + 1;
-            const int ae = (w + 1) * PK + lane + 1;
-            const int64_t p = (i * g.ny + j) * g.nz + k;
-            T e0 = sE[eb][0][ae], e1 = sE[eb][1][ae], e2 = sE[eb][2][ae];
-            e_cell<T>(g, pl, c, Hinc, sval, i, j, k, sH[eb][0][a], sH[eb][1][a], sH[eb][2][a],
-                      sH[eb][0][a - HK], sH[eb][0][a - 1], sH[hp][1][a], sH[eb][1][a - 1], sH[hp][2][a],
-                      sH[eb][2][a - HK], e0, e1, e2);
+        if (i + 1 < i1) load(i + 1, nxt);
+        T hx = cur.h[0], hy = cur.h[1], hz = cur.h[2];
+        if (vk)
+            h_cell<T>(g, c, Einc, gi, j, k, cur.e[0], cur.e[1], cur.e[2], cur.exj, cur.exk, cur.eyi, cur.eyk,
+                      cur.ezi, cur.ezj, hx, hy, hz, own && !lead);
+        const T hxk = lane_up1(hx), hyk = lane_up1(hy);   // H at k-1
+        if (own && !lead) {
+            T mx = cur.hmx, my = zero, mz = cur.hmz;
+            if (hasjm)
+                h_cell<T>(g, c, Einc, gi, jm, k, cur.m[0], cur.m[1], cur.m[2], cur.e[0], zero, cur.myi, cur.myk,
+                          zero, cur.e[2], mx, my, mz, false);
+            T e0 = cur.e[0], e1 = cur.e[1], e2 = cur.e[2];
+            const bool kin = k > 0;
+            e_cell<T>(g, pl, pn, c, Hinc, sval, gi, j, k, hx, hy, hz, hasjm ? mx : zero, kin ? hxk : zero, hy_i,
+                      kin ? hyk : zero, hz_i, hasjm ? mz : zero, e0, e1, e2);
+            const int64_t p = (gi * g.ny + j) * g.nz + k;
+            fout.H[0][p] = hx;
+            fout.H[1][p] = hy;
+            fout.H[2][p] = hz;
             fout.E[0][p] = e0;
             fout.E[1][p] = e1;
             fout.E[2][p] = e2;
         }
-        __syncthreads();
+        hy_i = hy;
+        hz_i = hz;
+        cur = nxt;
+        sp = spn;
+        of = ofn;
     }
 }
 
@@ -571,8 +652,8 @@ static dim3 grid3(const Geo3 &g)
 
 template <typename T>
 void launch_coef3d(const double *const w[3], const double *const n[3], int64_t S, double dt, double d,
-                   T *const eA[3], T *const eJ[3], T *const eH[3], double *const a[3], double *const b1[3],
-                   double *const b2[3], hipStream_t st)
+                   T *const eA[3], T *const eJ[3], T *const eH[3], T *const a[3], T *const b1[3],
+                   T *const b2[3], hipStream_t st)
 {
     if (S <= 0) return;
     hipLaunchKernelGGL(k_coef3d<T>, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st, w[0], w[1], w[2], n[0],
@@ -604,7 +685,8 @@ void launch_fused3d(const Geo3 &g, const Fields3<T> &fin, const Fields3<T> &fout
                     const Cpml3<T> &c, const double *Einc, const double *Hinc, double sval, int ni,
                     hipStream_t st)
 {
-    const int64_t nb = g.kb * g.jb * ((g.nx + ni - 1) / ni);
+    // 63 cells along k per wave (see k_fused3d)
+    const int64_t nb = ((g.nz + 62) / 63) * g.jb * ((g.nx + ni - 1) / ni);
     hipLaunchKernelGGL(k_fused3d<T>, dim3((unsigned)nb), dim3(256), 0, st, g, fin, fout, pl, c, Einc, Hinc,
                        sval, ni);
 }
@@ -664,8 +746,8 @@ void launch_copy3d(void *dst, const void *src, int64_t bytes, hipStream_t st)
     template void launch_flush3d<T>(const T *, int, int64_t, const int64_t *, int64_t, int,             \
                                     const double2 *, double2 *, hipStream_t);                             \
     template void launch_coef3d<T>(const double *const[3], const double *const[3], int64_t, double,     \
-                                   double, T *const[3], T *const[3], T *const[3], double *const[3],      \
-                                   double *const[3], double *const[3], hipStream_t);
+                                   double, T *const[3], T *const[3], T *const[3], T *const[3],           \
+                                   T *const[3], T *const[3], hipStream_t);
 INST3(float)
 INST3(double)
 #undef INST3
