@@ -743,6 +743,14 @@ def main():
     if not args.no_legs:
         out["batched"] = batched_leg()
         out["batched"]["vs_plain"] = round(out["batched"]["value"] / out["value"], 3)
+        # the same node class: the plain workload is half vacuum (whose tiles
+        # run about twice as fast), the batch 97% plasma; its whole-job rate
+        # against the plain run's plasma-tile rate (kernel time only)
+        if "tiled_plasma" in prof:
+            ms_t, calls, units = prof["tiled_plasma"]
+            rate = units / calls * tune["steps_per_pass"] / (ms_t / calls / 1e3) / 1e6
+            out["batched"]["plain_plasma_tile_rate"] = round(rate, 1)
+            out["batched"]["vs_plain_plasma_tiles"] = round(out["batched"]["value"] / rate, 3)
         out["adjoint"] = adjoint_leg()
         out["c1_latency"] = c1_leg()
         out["c3_3d"] = c3_leg()
