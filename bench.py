@@ -658,6 +658,7 @@ def main():
                     help="run just this leg and print its JSON (profiling runs)")
     ap.add_argument("--c3-steps", type=int, default=2000)
     ap.add_argument("--c3-exec", default="auto", choices=["auto", "split", "fused"])
+    ap.add_argument("--c2d-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -683,7 +684,7 @@ def main():
         del x, y
     if args.only:
         leg = {"c3": lambda: c3_leg(T=args.c3_steps, exec=args.c3_exec), "batched": batched_leg, "adjoint": adjoint_leg,
-               "c1": c1_leg, "table2": table2_leg, "c2d": c2d_leg}[args.only]
+               "c1": c1_leg, "table2": table2_leg, "c2d": lambda: c2d_leg(T=args.c2d_steps)}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     from paper_1709_00821_amd import workloads as W
