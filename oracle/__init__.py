@@ -18,10 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRCS = ["rketd1d.c", "adjoint1d.c", "rketd3d.c", "rketd2d.c"]
 _lib = None
-# timing builds of the same sources (the benchmark's CPU-baseline leg only):
-# "native" is the serial oracle with -O3 -march=native, "omp" adds -fopenmp
-# (the 1D node loops carry OpenMP pragmas, ignored by the other builds).
-# Every build keeps -ffp-contract=off, so all give the same results.
+# faster builds of the same sources: "native" is the serial oracle with -O3
+# -march=native, "omp" adds -fopenmp (the 1D node loops and the 2D cell loops
+# carry OpenMP pragmas, ignored by the other builds; their iterations are
+# independent, so the order of the arithmetic is unchanged).  Every build
+# keeps -ffp-contract=off, so all give the same results bit for bit.  Used by
+# the benchmark's CPU-baseline leg and by the largest parity cases.
 _TIMING = {"native": ["-O3", "-march=native"], "omp": ["-O3", "-march=native", "-fopenmp"]}
 _timing_libs = {}
 

@@ -93,6 +93,7 @@ int or2d_step(const or2d_problem *pb, or2d_state *st, int64_t nsteps)
     for (int64_t it = 0; it < nsteps; ++it) {
         /* H^{n+1/2} from E^n (new values into Hn, then copied: every H update
            reads only E) */
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nx; ++i)
             for (int64_t j = 0; j < ny; ++j) {
                 const int64_t k = i * ny + j;
@@ -111,6 +112,7 @@ int or2d_step(const or2d_problem *pb, or2d_state *st, int64_t nsteps)
 
         /* E^{n+1} from E^n, J^n, H^{n+1/2}: eqs.(11)+(12) solved together */
         for (int c = 0; c < nc; ++c) memcpy(Eold[c], st->E[c], sizeof(double) * (size_t)N);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nx; ++i)
             for (int64_t j = 0; j < ny; ++j) {
                 const int64_t k = i * ny + j;
@@ -142,6 +144,7 @@ int or2d_step(const or2d_problem *pb, or2d_state *st, int64_t nsteps)
         }
         /* J^{n+1}, eq.(11) */
         for (int c = 0; c < nc; ++c)
+#pragma omp parallel for schedule(static)
             for (int64_t k = 0; k < N; ++k) {
                 const double *q = cf[c] + 9 * k;
                 st->J[c][k] = q[0] * st->J[c][k] + q[7] * Eold[c][k] + q[8] * st->E[c][k];

@@ -106,3 +106,51 @@ def test_2d_errors(G):
         with pytest.raises(L.FdtdError) as e:
             h.spectra()
         assert e.value.code == L.E_STATE
+
+
+def _crop2(p, i0, i1, j0, j1):
+    """The sub-box [i0, i1) x [j0, j1) of p as its own walled problem, the
+    source and the probes inside it moved with it."""
+    keep = [(k, c, i - i0, j - j0) for k, (c, i, j) in enumerate(p.probes) if i0 <= i < i1 and j0 <= j < j1]
+    probes = np.array([q[1:] for q in keep], np.int64).reshape(-1, 3)
+    q = p.copy(nx=i1 - i0, ny=j1 - j0, wp2=np.ascontiguousarray(p.wp2[:, i0:i1, j0:j1]),
+               nu=np.ascontiguousarray(p.nu[:, i0:i1, j0:j1]), src=(p.src[0] - i0, p.src[1] - j0),
+               probes=probes)
+    return q, [k for k, *_ in keep]
+
+
+@pytest.mark.parametrize("mode", ["tm", "te"])
+def test_cylinder_2d_full_size_light_cone_matches_oracle(G, mode):
+    """The 4096^2 benchmark problem in the benchmark's launch configuration
+    (run(T), graph replay), T = 800 steps, against the oracle on the box of
+    cells within T + 4 of the source: a step moves the fields one cell along
+    each axis, so outside that box the full-size fields are exactly zero and
+    inside it the box's walls, never reached, change nothing.  By step 800
+    the pulse (half a cell a step) has entered the cylinder's Gaussian edge,
+    320 cells from the source, so support cells carry current."""
+    n, T = 4096, 800
+    p = W.cylinder_2d(mode, n=n, n_freqs=16)
+    si, sj = p.src
+    r = T + 4
+    i0, i1, j0, j1 = si - r, si + r + 1, sj - r, sj + r + 1
+    q, inside = _crop2(p, i0, i1, j0, j1)
+    assert q.wp2.any(), "the box must hold plasma"
+    say(f"case 2d cylinder full size {mode} n={n} steps={T} box {q.nx}x{q.ny}")
+    o = oracle.run2d(q, T, kind="omp")      # the OpenMP build: the same bits, sooner
+    for prec, tol in (("f64", 1e-12), ("f32", 2e-5)):
+        with G.FdtdPlasma2D(p, precision=prec) as h:
+            h.run(T)
+            F = h.fields()
+            X = h.spectra()
+        for k in ("E", "H", "J"):
+            out = F[k].copy()
+            out[:, i0:i1, j0:j1] = 0.0
+            assert np.count_nonzero(out) == 0, (prec, k, "nonzero outside the light cone")
+        Fin = {k: F[k][:, i0:i1, j0:j1] for k in ("E", "H", "J")}
+        ef = errs(Fin, o)
+        outside = [k for k in range(len(p.probes)) if k not in inside]
+        assert np.all(X[outside] == 0)
+        ex = rel(X[inside], o["X"]) if inside else 0.0
+        say(f"2d full size {mode} {prec}: fields E {ef[0]:.2e} H {ef[1]:.2e} J {ef[2]:.2e} spectra {ex:.2e}")
+        assert max(ef) <= tol * 10 and ex <= tol, prec
+    assert np.max(np.abs(o["J"])) > 0

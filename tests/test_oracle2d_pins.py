@@ -194,3 +194,16 @@ def test_courant_limit_2d():
     assert oracle.check2(p) == 0
     q = p.copy(dt=0.75 * p.d / C0)
     assert oracle.check2(q) == -2
+
+
+def test_openmp_build_gives_the_same_bits():
+    """The OpenMP build (cell loops in parallel, used for the largest parity
+    case) and the -O3 -march=native build equal the plain build bit for bit."""
+    rng = np.random.default_rng(31)
+    for mode, px in (("tm", False), ("te", True)):
+        p = W.random_2d(rng, mode, 40, 52, periodic_x=px)
+        a = oracle.run2d(p, 120)
+        for kind in ("omp", "native"):
+            b = oracle.run2d(p, 120, kind=kind)
+            for k in ("E", "H", "J", "X"):
+                assert np.array_equal(a[k], b[k]), (mode, kind, k)
