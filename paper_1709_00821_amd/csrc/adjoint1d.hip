@@ -328,105 +328,116 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
     const int p_lane = uniform(has_p ? (pc - tl.lo) / C : -1), p_reg = uniform(has_p ? (pc - tl.lo) % C : 0);
     const int nn = (int)n;
     auto slotp = [&](int64_t m, int q) { return a.seg + (m - a.m0) * a.slot_bytes + q * a.arr_bytes; };
-    // forward states E^m, J^m, H^{m+1/2}, E^{m+1} of the next step are loaded
-    // one step ahead (E^{m+1} of step m-1 is this step's E^m)
-    T ne0[C], nhh[C], ne1[C];
-    double nj0[C];
-    load_chunk<T, C>((const T *)slotp(mtop, 0) + off, k0, tl.hi, ne0);
-    load_chunk<double, C>((const double *)slotp(mtop, 2) + off, k0, tl.hi, nj0);
-    load_chunk<T, C>((const T *)slotp(mtop + 1, 1) + off, k0, tl.hi, nhh);
-    load_chunk<T, C>((const T *)slotp(mtop + 1, 0) + off, k0, tl.hi, ne1);
-    for (int st = 0; st < nsteps; ++st) {
+    // forward states of step st (m = mtop - st): E^m and P^{m-1} (slot m),
+    // H^{m+1/2} (slot m+1), and E^{m+1}, which is step st-1's E^m.  The first
+    // three (and the probe's adjoint source) are loaded kAdjPrefetch steps
+    // ahead into a ring of registers: they do not depend on the adjoint
+    // arithmetic, and a step waits only on the loads issued for it.
+    constexpr int D = kAdjPrefetch;
+    T qe[D][C], qh[D][C];
+    double qj[D][C], qs[D];
+    auto fetch = [&](int st, T (&e)[C], double (&j)[C], T (&h)[C], double &sv) {
         const int64_t m = mtop - st;
-        T e0[C], hh[C], e1[C];
-        double j0[C];
+        load_chunk<T, C>((const T *)slotp(m, 0) + off, k0, tl.hi, e);
+        load_chunk<double, C>((const double *)slotp(m, 2) + off, k0, tl.hi, j);
+        load_chunk<T, C>((const T *)slotp(m + 1, 1) + off, k0, tl.hi, h);
+        sv = has_p ? a.gsrc[(int64_t)b * a.T_ + m] : 0.0;
+    };
 #pragma unroll
-        for (int i = 0; i < C; ++i) {
-            e0[i] = ne0[i];
-            j0[i] = nj0[i];
-            hh[i] = nhh[i];
-            e1[i] = ne1[i];
-        }
-        if (st + 1 < nsteps) {
+    for (int d = 0; d < D; ++d)
+        if (d < nsteps) fetch(d, qe[d], qj[d], qh[d], qs[d]);
+    T e1[C];
+    load_chunk<T, C>((const T *)slotp(mtop + 1, 0) + off, k0, tl.hi, e1);
+    for (int base = 0; base < nsteps; base += D) {
 #pragma unroll
-            for (int i = 0; i < C; ++i) ne1[i] = e0[i];
-            load_chunk<T, C>((const T *)slotp(m - 1, 0) + off, k0, tl.hi, ne0);
-            load_chunk<double, C>((const double *)slotp(m - 1, 2) + off, k0, tl.hi, nj0);
-            load_chunk<T, C>((const T *)slotp(m, 1) + off, k0, tl.hi, nhh);
-        }
-        const double src = has_p ? a.gsrc[(int64_t)b * a.T_ + m] : 0.0;
-        double lEp[C], es[C], lHn[C];
+        for (int d = 0; d < D; ++d) {
+            const int st = base + d;
+            if (st >= nsteps) break;
+            T e0[C], hh[C];
+            double j0[C];
 #pragma unroll
-        for (int i = 0; i < C; ++i) {
-            const double l = (double)lE[i];
-            lEp[i] = (ROLE && lane == p_lane && i == p_reg) ? l + src : l;
-        }
-        double lEp0 = 0.0, lEpN = 0.0;
-        if constexpr (ROLE) {
-            // lEp at node 0 for node 1 (same lane: node 0 sits in register 0
-            // or 1 of lane 0), at node n-1 for node n-2 (same lane, or the
-            // next lane's register 0)
-            const int r0 = uniform(tl.lo <= 0 ? -tl.lo : 0);
-            lEp0 = upick<double, C>(lEp, r0);
-            const int64_t pr = n - 1 - tl.lo;
-            const int rr = uniform(pr >= 0 && pr < 64LL * C ? pr % C : 1);
-            const double nx = shfl_down1(lEp[0]);
-            const double own = upick<double, C>(lEp, rr);
-            lEpN = (rr > 0) ? own : nx;
-        }
-#pragma unroll
-        for (int i = 0; i < C; ++i) {
-            double s = lEp[i];
-            if constexpr (ROLE) {
-                const int k = (int)(k0 + i);
-                s = (mur && k == 1) ? s + cm * lEp0 : s;
-                s = (mur && k == nn - 2) ? s + cm * lEpN : s;
+            for (int i = 0; i < C; ++i) {
+                e0[i] = qe[d][i];
+                j0[i] = qj[d][i];
+                hh[i] = qh[d][i];
             }
-            es[i] = s + B2[i] * (double)lJ[i];
-        }
-        const double esn = shfl_down1(es[0]);
+            const double src = qs[d];
+            if (st + D < nsteps) fetch(st + D, qe[d], qj[d], qh[d], qs[d]);
+            double lEp[C], es[C], lHn[C];
 #pragma unroll
-        for (int i = 0; i < C; ++i) {
-            const double en = (i + 1 < C) ? es[i + 1] : esn;
-            double s = (double)lH[i];
-            if constexpr (ROLE) {
-                const int k = (int)(k0 + i);
-                s = (k + 1 <= nn - 2) ? s + CHn[i] * en : s;
-                s = (k >= 1) ? s - CH[i] * es[i] : s;
-            } else {
-                s += CHn[i] * en;
-                s -= CH[i] * es[i];
+            for (int i = 0; i < C; ++i) {
+                const double l = (double)lE[i];
+                lEp[i] = (ROLE && lane == p_lane && i == p_reg) ? l + src : l;
             }
-            lHn[i] = s;
-        }
-        const double lHp = shfl_up1(lHn[C - 1]);
-        const T hhp = shfl_up1(hh[C - 1]);
+            double lEp0 = 0.0, lEpN = 0.0;
+            if constexpr (ROLE) {
+                // lEp at node 0 for node 1 (same lane: node 0 sits in register 0
+                // or 1 of lane 0), at node n-1 for node n-2 (same lane, or the
+                // next lane's register 0)
+                const int r0 = uniform(tl.lo <= 0 ? -tl.lo : 0);
+                lEp0 = upick<double, C>(lEp, r0);
+                const int64_t pr = n - 1 - tl.lo;
+                const int rr = uniform(pr >= 0 && pr < 64LL * C ? pr % C : 1);
+                const double nx = shfl_down1(lEp[0]);
+                const double own = upick<double, C>(lEp, rr);
+                lEpN = (rr > 0) ? own : nx;
+            }
 #pragma unroll
-        for (int i = 0; i < C; ++i) {
-            const double lhm = (i > 0) ? lHn[i - 1] : lHp;
-            const double lj = (double)lJ[i];
-            double nJ = A[i] * lj - CJ[i] * es[i];
-            double nE = CA[i] * es[i] + B1[i] * lj + ch * (lHn[i] - lhm);
-            const double curl = (double)hh[i] - (double)((i > 0) ? hh[i - 1] : hhp);
-            const double e0d = (double)e0[i], e1d = (double)e1[i];
-            const double jm = __builtin_fma(B2[i], e0d, j0[i]);   // J^m from the stored P^{m-1}
-            const double gnew =
-                gr[i] + (es[i] * (dCA[i] * e0d - dCJ[i] * jm - dCH[i] * curl) + lj * (dB1[i] * e0d + dB2[i] * e1d));
-            if constexpr (ROLE) {
-                const int k = (int)(k0 + i);
-                nE = (mur && k == 1) ? nE + lEp0 : nE;
-                nE = (mur && k == nn - 2) ? nE + lEpN : nE;
-                const bool end = k == 0 || k == nn - 1;
-                const double nEe = mur ? -cm * lEp[i] + (k == 0 ? ch * lHn[i] : -ch * lhm) : 0.0;
-                nE = end ? nEe : nE;
-                nJ = end ? 0.0 : nJ;
-                gr[i] = (k >= 1 && k <= nn - 2) ? gnew : gr[i];
-            } else {
-                gr[i] = gnew;
+            for (int i = 0; i < C; ++i) {
+                double s = lEp[i];
+                if constexpr (ROLE) {
+                    const int k = (int)(k0 + i);
+                    s = (mur && k == 1) ? s + cm * lEp0 : s;
+                    s = (mur && k == nn - 2) ? s + cm * lEpN : s;
+                }
+                es[i] = s + B2[i] * (double)lJ[i];
             }
-            lE[i] = (T)nE;
-            lJ[i] = (T)nJ;
-            lH[i] = (T)lHn[i];
+            const double esn = shfl_down1(es[0]);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const double en = (i + 1 < C) ? es[i + 1] : esn;
+                double s = (double)lH[i];
+                if constexpr (ROLE) {
+                    const int k = (int)(k0 + i);
+                    s = (k + 1 <= nn - 2) ? s + CHn[i] * en : s;
+                    s = (k >= 1) ? s - CH[i] * es[i] : s;
+                } else {
+                    s += CHn[i] * en;
+                    s -= CH[i] * es[i];
+                }
+                lHn[i] = s;
+            }
+            const double lHp = shfl_up1(lHn[C - 1]);
+            const T hhp = shfl_up1(hh[C - 1]);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const double lhm = (i > 0) ? lHn[i - 1] : lHp;
+                const double lj = (double)lJ[i];
+                double nJ = A[i] * lj - CJ[i] * es[i];
+                double nE = CA[i] * es[i] + B1[i] * lj + ch * (lHn[i] - lhm);
+                const double curl = (double)hh[i] - (double)((i > 0) ? hh[i - 1] : hhp);
+                const double e0d = (double)e0[i], e1d = (double)e1[i];
+                const double jm = __builtin_fma(B2[i], e0d, j0[i]);   // J^m from the stored P^{m-1}
+                const double gnew =
+                    gr[i] + (es[i] * (dCA[i] * e0d - dCJ[i] * jm - dCH[i] * curl) + lj * (dB1[i] * e0d + dB2[i] * e1d));
+                if constexpr (ROLE) {
+                    const int k = (int)(k0 + i);
+                    nE = (mur && k == 1) ? nE + lEp0 : nE;
+                    nE = (mur && k == nn - 2) ? nE + lEpN : nE;
+                    const bool end = k == 0 || k == nn - 1;
+                    const double nEe = mur ? -cm * lEp[i] + (k == 0 ? ch * lHn[i] : -ch * lhm) : 0.0;
+                    nE = end ? nEe : nE;
+                    nJ = end ? 0.0 : nJ;
+                    gr[i] = (k >= 1 && k <= nn - 2) ? gnew : gr[i];
+                } else {
+                    gr[i] = gnew;
+                }
+                lE[i] = (T)nE;
+                lJ[i] = (T)nJ;
+                lH[i] = (T)lHn[i];
+            }
+#pragma unroll
+            for (int i = 0; i < C; ++i) e1[i] = e0[i];
         }
     }
 }

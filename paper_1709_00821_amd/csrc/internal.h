@@ -134,7 +134,7 @@ void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64
 template <typename T>
 void launch_trace(const Grids &g, char *seg, int64_t slot_bytes, int64_t arr_bytes, const Tile *tiles,
                   int64_t ntiles, int nsteps, int slot0, hipStream_t st);
-constexpr int kTraceCells = 256, kTraceHalo = 48;
+constexpr int kTraceCells = 128, kTraceHalo = 48;
 
 // Reverse sweep on register tiles (kAdjCells nodes, kAdjHalo halo): nsteps
 // transposed steps m = mtop, mtop - 1, .. per launch.
@@ -155,7 +155,8 @@ struct AdjTileArgs {
 template <typename T>
 void launch_adj_tiled(const Grids &g, const AdjTileArgs<T> &a, const Tile *tiles, int64_t ntiles, int64_t mtop,
                       int nsteps, hipStream_t st);
-constexpr int kAdjCells = 256, kAdjHalo = 48;
+constexpr int kAdjCells = 128, kAdjHalo = 48;
+constexpr int kAdjPrefetch = 6;   // steps of forward state the reverse sweep loads ahead
 
 // Reads buffer cur, writes buffer out (cur itself for a whole-run resident
 // call, the other buffer when bins and tiles share a pass).

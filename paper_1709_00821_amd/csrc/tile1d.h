@@ -88,18 +88,37 @@ __device__ __forceinline__ double shfl_up1(double x)
     return __builtin_bit_cast(double, make_int2(dpp_up1(v.x), dpp_up1(v.y)));
 }
 
+// The vector a lane moves C nodes of T with: 16 bytes, or the whole chunk
+// where it is smaller (C = 2 in FP32).
+template <int B>
+struct VecOf;
+template <>
+struct VecOf<16> {
+    typedef uint4 type;
+};
+template <>
+struct VecOf<8> {
+    typedef uint2 type;
+};
+template <typename T, int C>
+struct ChunkVec {
+    static constexpr int bytes = C * (int)sizeof(T) >= 16 ? 16 : C * (int)sizeof(T);
+    static constexpr int per = bytes / (int)sizeof(T);
+    typedef typename VecOf<bytes>::type type;
+    static_assert(C % per == 0, "C must fill whole vectors");
+};
+
 // Load nodes [k0, k0+C) of array a (grid-local pointer); nodes >= lim read 0.
 template <typename T, int C>
 __device__ __forceinline__ void load_chunk(const T *a, int64_t k0, int64_t lim, T (&v)[C])
 {
-    constexpr int per16 = 16 / (int)sizeof(T);
-    if (k0 >= 0 && k0 + C <= lim && (k0 % per16) == 0) {
-        constexpr int per = per16;
-        static_assert(C % per == 0, "C must fill 16-byte vectors");
-        const uint4 *p = reinterpret_cast<const uint4 *>(a + k0);
+    typedef ChunkVec<T, C> CV;
+    constexpr int per = CV::per;
+    if (k0 >= 0 && k0 + C <= lim && (k0 % per) == 0) {
+        const typename CV::type *p = reinterpret_cast<const typename CV::type *>(a + k0);
 #pragma unroll
         for (int q = 0; q < C / per; ++q) {
-            const uint4 u = p[q];
+            const typename CV::type u = p[q];
             const T *t = reinterpret_cast<const T *>(&u);
 #pragma unroll
             for (int r = 0; r < per; ++r) v[q * per + r] = t[r];
@@ -114,13 +133,13 @@ __device__ __forceinline__ void load_chunk(const T *a, int64_t k0, int64_t lim, 
 template <typename T, int C>
 __device__ __forceinline__ void store_chunk(T *a, int64_t k0, int64_t lo, int64_t hi, const T (&v)[C])
 {
-    constexpr int per16 = 16 / (int)sizeof(T);
-    if (k0 >= lo && k0 + C <= hi && (k0 % per16) == 0) {
-        constexpr int per = per16;
-        uint4 *p = reinterpret_cast<uint4 *>(a + k0);
+    typedef ChunkVec<T, C> CV;
+    constexpr int per = CV::per;
+    if (k0 >= lo && k0 + C <= hi && (k0 % per) == 0) {
+        typename CV::type *p = reinterpret_cast<typename CV::type *>(a + k0);
 #pragma unroll
         for (int q = 0; q < C / per; ++q) {
-            uint4 u;
+            typename CV::type u;
             T *t = reinterpret_cast<T *>(&u);
 #pragma unroll
             for (int r = 0; r < per; ++r) t[r] = v[q * per + r];
