@@ -89,7 +89,7 @@ typedef struct {
     int32_t precision;           /* FDTD_F64: E, H (and psi) stored in FP64.  FDTD_F32: stored in
                                     FP32, the updates computed in FP64 registers and rounded to
                                     FP32 only where a launch stores the fields (see the exec
-                                    modes).  J (carried as J - b2 E) and its eq.(11) update are
+                                    modes).  J (carried as CJ (J - b2 E)) and its eq.(11) update are
                                     FP64 at either precision; the DFT is FP64.
                                     FDTD_F32_DELTA: an accuracy ablation with every field update in
                                     FP32 arithmetic (fields rounded to FP32 after every operation),

@@ -22,8 +22,9 @@ __device__ __forceinline__ int grid_of_adj(const Grids &g, int64_t i)
     return (int)lo;
 }
 
-// Per-node coefficients and their wp2-derivatives, SoA [11][nodes]:
-// CA, CJ, CH, a, b1, b2, dCA, dCJ, dCH, db1, db2.
+// Per-node coefficients and their wp2-derivatives, SoA [12][nodes]:
+// CA, CJ, CH, a, b1, b2, dCA, dCJ, dCH, db1, db2, 1/CJ (the last turns the
+// forward state's carried Q = CJ (J - b2 E) back into J).
 __global__ void k_adj_coef(Grids g, int64_t total, double *tab)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,9 +32,9 @@ __global__ void k_adj_coef(Grids g, int64_t total, double *tab)
     const double w = g.wp2[i], v = g.nu[i];
     const Coef c = node_coef(w, v, g.dt, g.dz, 0);
     const DCoef d = node_dcoef(w, v, g.dt, g.dz);
-    const double vals[11] = {c.CA, c.CJ, c.CH, c.a, c.b1, c.b2, d.dCA, d.dCJ, d.dCH, d.db1, d.db2};
+    const double vals[12] = {c.CA, c.CJ, c.CH, c.a, c.b1, c.b2, d.dCA, d.dCJ, d.dCH, d.db1, d.db2, 1.0 / c.CJ};
 #pragma unroll
-    for (int q = 0; q < 11; ++q) tab[(int64_t)q * total + i] = vals[q];
+    for (int q = 0; q < 12; ++q) tab[(int64_t)q * total + i] = vals[q];
 }
 
 // Per grid: R_f, loss_b = sum_f |R_f|^2 and G_f = conj(R_f) / Xref_f.  One wave
@@ -83,7 +84,7 @@ struct AdjView {
     const T *lE, *lH, *lJ;      // lambda^{m+1}
     T *nE, *nH, *nJ;            // lambda^m
     const T *En;                // forward E^m
-    const double *Jn;           // forward P^{m-1} = J^m - b2 E^m (FP64)
+    const double *Jn;           // forward Q^{m-1} = CJ (J^m - b2 E^m) (FP64)
     const T *Hh, *En1;          // forward H^{m+1/2}, E^{m+1}
 };
 
@@ -140,8 +141,9 @@ __global__ void k_adj_step(Grids g, AdjView<T> v, const double *tab, int64_t tot
         const double dCA = tab[6 * total + off + k], dCJ = tab[7 * total + off + k];
         const double dCH = tab[8 * total + off + k], dB1 = tab[9 * total + off + k];
         const double dB2 = tab[10 * total + off + k];
-        // the stored forward state carries P^{m-1} = J^m - b2 E^m
-        const double e0 = (double)v.En[off + k], j0 = __builtin_fma(B2[off + k], e0, v.Jn[off + k]);
+        // the stored forward state carries Q^{m-1} = CJ (J^m - b2 E^m)
+        const double e0 = (double)v.En[off + k];
+        const double j0 = __builtin_fma(B2[off + k], e0, v.Jn[off + k] * tab[11 * total + off + k]);
         const double curl = (double)v.Hh[off + k] - (double)v.Hh[off + k - 1];
         const double e1 = (double)v.En1[off + k];
         grad[off + k] += es * (dCA * e0 - dCJ * j0 - dCH * curl) + lj * (dB1 * e0 + dB2 * e1);
@@ -280,7 +282,7 @@ template void launch_trace<double>(const Grids &, char *, int64_t, int64_t, cons
 
 // Transposed steps of the adjoint on register tiles: lane holds C nodes of
 // lambda_E, lambda_H, lambda_J (storage precision, as between the steps of
-// the per-step kernel), the eleven coefficient and derivative values and the
+// the per-step kernel), the twelve coefficient and derivative values and the
 // gradient of its nodes (FP64).  Reverse step m (lambda^{m+1} -> lambda^m),
 // for interior nodes k, with es the adjoint of the E update's input, lHn the
 // adjoint of H^{m+1/2}:
@@ -303,7 +305,7 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
                                                double (&gr)[C])
 {
     const int64_t tot = a.total;
-    double CA[C], CJ[C], CH[C], CHn[C], A[C], B1[C], B2[C], dCA[C], dCJ[C], dCH[C], dB1[C], dB2[C];
+    double CA[C], CJ[C], CH[C], CHn[C], A[C], B1[C], B2[C], dCA[C], dCJ[C], dCH[C], dB1[C], dB2[C], ICJ[C];
     load_chunk<double, C>(a.tab + 0 * tot + off, k0, tl.hi, CA);
     load_chunk<double, C>(a.tab + 1 * tot + off, k0, tl.hi, CJ);
     load_chunk<double, C>(a.tab + 2 * tot + off, k0, tl.hi, CH);
@@ -315,6 +317,7 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
     load_chunk<double, C>(a.tab + 8 * tot + off, k0, tl.hi, dCH);
     load_chunk<double, C>(a.tab + 9 * tot + off, k0, tl.hi, dB1);
     load_chunk<double, C>(a.tab + 10 * tot + off, k0, tl.hi, dB2);
+    load_chunk<double, C>(a.tab + 11 * tot + off, k0, tl.hi, ICJ);
     {
         const double nx = shfl_down1(CH[0]);
 #pragma unroll
@@ -328,7 +331,7 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
     const int p_lane = uniform(has_p ? (pc - tl.lo) / C : -1), p_reg = uniform(has_p ? (pc - tl.lo) % C : 0);
     const int nn = (int)n;
     auto slotp = [&](int64_t m, int q) { return a.seg + (m - a.m0) * a.slot_bytes + q * a.arr_bytes; };
-    // forward states of step st (m = mtop - st): E^m and P^{m-1} (slot m),
+    // forward states of step st (m = mtop - st): E^m and Q^{m-1} (slot m),
     // H^{m+1/2} (slot m+1), and E^{m+1}, which is step st-1's E^m.  The first
     // three (and the probe's adjoint source) are loaded kAdjPrefetch steps
     // ahead into a ring of registers: they do not depend on the adjoint
@@ -417,7 +420,7 @@ __device__ __forceinline__ void adj_tile_steps(const Grids &g, const AdjTileArgs
                 double nE = CA[i] * es[i] + B1[i] * lj + ch * (lHn[i] - lhm);
                 const double curl = (double)hh[i] - (double)((i > 0) ? hh[i - 1] : hhp);
                 const double e0d = (double)e0[i], e1d = (double)e1[i];
-                const double jm = __builtin_fma(B2[i], e0d, j0[i]);   // J^m from the stored P^{m-1}
+                const double jm = __builtin_fma(B2[i], e0d, j0[i] * ICJ[i]);   // J^m from the stored Q^{m-1}
                 const double gnew =
                     gr[i] + (es[i] * (dCA[i] * e0d - dCJ[i] * jm - dCH[i] * curl) + lj * (dB1[i] * e0d + dB2[i] * e1d));
                 if constexpr (ROLE) {

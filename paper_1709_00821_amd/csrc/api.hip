@@ -548,7 +548,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
         for (int i = 0; i < 2; ++i)
             for (int q = 0; q < 3; ++q) p.o_lam[i][q] = L.take(p.state_bytes);
         p.o_grad = L.take(8 * p.nodes);
-        p.o_tab = L.take(8 * 11 * p.nodes);
+        p.o_tab = L.take(8 * 12 * p.nodes);
         p.o_gsrc = L.take(8 * d->batch * p.ck_T);
         // the reverse sweep recomputes each segment with register tiles of
         // kTraceCells nodes, kTraceHalo steps per launch
@@ -1215,14 +1215,17 @@ int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, d
     if ((rc = fetch(h->d_H[h->cur], H, n - 1, h->esize))) return rc;
     if ((rc = fetch(h->d_J[h->cur], J, n, 8))) return rc;
     if (J && h->d.precision != FDTD_F32_DELTA) {
-        // the state carries P^{n-1} = J^n - b2 E^n: J^n = P + b2 E^n, with b2 of
-        // eq.(11) from the node's wp2 and nu
+        // the state carries Q^{n-1} = CJ (J^n - b2 E^n): J^n = Q / CJ + b2 E^n,
+        // with CJ and b2 of eqs.(11)+(13) from the node's wp2 and nu
         std::vector<double> En(n), w(n), v(n);
         if ((rc = fetch(h->d_E[h->cur], En.data(), n, h->esize))) return rc;
         if ((rc = fetch(h->d_wp2, w.data(), n, 8))) return rc;
         if ((rc = fetch(h->d_nu, v.data(), n, 8))) return rc;
         for (int64_t k = 0; k < n; ++k)
-            if (w[k] != 0.0) J[k] = std::fma(node_coef(w[k], v[k], h->d.dt, h->d.dz, h->d.scheme).b2, En[k], J[k]);
+            if (w[k] != 0.0) {
+                const Coef c = node_coef(w[k], v[k], h->d.dt, h->d.dz, h->d.scheme);
+                J[k] = std::fma(c.b2, En[k], J[k] / c.CJ);
+            }
     }
     return FDTD_OK;
 }

@@ -39,7 +39,7 @@ struct State {
     T *E[2];
     T *H[2];
     double *J[2];           // the plasma current, in FP64 at either field precision, carried as
-                            // P^{n-1} = J^n - b2 E^n (the FP32 ablation: J^n itself)
+                            // Q^{n-1} = CJ (J^n - b2 E^n) (the FP32 ablation: J^n itself)
     T *psiE[2];             // [batch][2][P]: left zone then right zone
     T *psiH[2];
 };
@@ -142,10 +142,10 @@ template <typename T>
 struct AdjTileArgs {
     const T *lE, *lH, *lJ;      // lambda^{mtop+1} (read)
     T *nE, *nH, *nJ;            // lambda^{mtop+1-nsteps} (written, output nodes)
-    const double *tab;          // [11][total] coefficients and wp2-derivatives
+    const double *tab;          // [12][total] coefficients, wp2-derivatives and 1/CJ
     int64_t total;
     const char *seg;            // forward states: slot i = m - m0 (E, H at + arr_bytes, the carried
-                                // P = J - b2 E at + 2 arr_bytes)
+                                // Q = CJ (J - b2 E) at + 2 arr_bytes)
     int64_t slot_bytes, arr_bytes, m0;
     const double *gsrc;         // [batch][T_] dL/dE at the probe
     int64_t T_;

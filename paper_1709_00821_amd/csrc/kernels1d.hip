@@ -115,13 +115,13 @@ __device__ __forceinline__ R step_interior(const Grids &g, const State<T> &s, in
     }
     const R Eo = (R)s.E[cur][off + k];
     const double wp2 = g.wp2[off + k];
-    // the J arrays hold P^{n-1} = J^n - b2 E^n (the FP32 ablation: J^n itself)
+    // the J arrays hold Q^{n-1} = CJ (J^n - b2 E^n) (the FP32 ablation: J^n itself)
     const double Po = s.J[cur][off + k];
     R En;
     NodeCoef<R> c;
     if (wp2 != 0.0) {
         c = node_coef_t<R>(wp2, g.nu[off + k], g.dt, g.dz, g.scheme);
-        En = g.jdelta ? e_update_plasma(Eo, Po, curl, c) : e_update_plasma_p(Eo, Po, curl, c);
+        En = g.jdelta ? e_update_plasma(Eo, Po, curl, c) : e_update_plasma_q(Eo, Po, curl, c);
     } else {
         En = e_update_vac<R>(Eo, curl, (R)g.ce);
     }
@@ -133,7 +133,7 @@ __device__ __forceinline__ R step_interior(const Grids &g, const State<T> &s, in
             if constexpr (sizeof(R) == 4) {
                 Pn = (double)j_update_delta((float)Po, Eo, En, c.a, c.b1, c.b2);
             } else {
-                Pn = p_update<R>(Po, (double)Eo, c);
+                Pn = q_update<R>(Po, (double)Eo, c);
             }
         }
         s.J[nxt][off + k] = Pn;

@@ -209,12 +209,13 @@ template <typename T>
 struct NodeCoef {
     T eA, eJ, eH;
     double a, b1, b2;
-    // the 1D steps carry P^n = J^{n+1} - b2 E^{n+1} = a J^n + b1 E^n in place
-    // of J (one FP64 operation fewer a node-step): P^n = a P^{n-1} + pc E^n with
-    // pc = a b2 + b1, and E^{n+1} = (CA - CJ b2) E^n - CJ P^{n-1} - CH curl, the
-    // first coefficient held like eA (FP64: itself; FP32: minus 1)
+    // the 1D steps carry Q^n = CJ (J^{n+1} - b2 E^{n+1}) = CJ (a J^n + b1 E^n)
+    // in place of J (eq.(11) rearranged): Q^n = a Q^{n-1} + qc E^n with
+    // qc = CJ (a b2 + b1), and E^{n+1} = (CA - CJ b2) E^n - Q^{n-1} - CH curl,
+    // the first coefficient held like eA (FP64: itself; FP32: minus 1).  The
+    // E update is then two FMAs and the node holds no CJ.
     T eP;
-    double pc;
+    double qc;
 };
 
 template <typename T>
@@ -230,26 +231,31 @@ __host__ __device__ inline NodeCoef<T> node_coef_t(double wp2, double nu, double
     r.b1 = c.b1;
     r.b2 = c.b2;
     r.eP = sizeof(T) == 8 ? (T)(c.CA - c.CJ * c.b2) : (T)(c.CAm1 - c.CJ * c.b2);
-    r.pc = c.a * c.b2 + c.b1;
+    r.qc = c.CJ * (c.a * c.b2 + c.b1);
     return r;
 }
 
-// The E update on the carried P (the algebra above; J^n = P^{n-1} + b2 E^n),
-// and the P update, which reads E^n before the E update overwrites it.  At a
-// vacuum node (eP as eA, P = +0, pc = 0) these give the bits of the vacuum
-// update and keep P at +0.
-__device__ __forceinline__ double e_update_plasma_p(double E, double P, double curl, const NodeCoef<double> &c)
+// The E update on the carried Q (the algebra above; J^n = Q^{n-1} / CJ +
+// b2 E^n), and the Q update, which reads E^n before the E update overwrites
+// it.  At a vacuum node (eP as eA = 1, Q = +0, qc = 0) these give the bits of
+// the vacuum update, signed zeros included, and keep Q at +0.
+__device__ __forceinline__ double e_update_plasma_q(double E, double Q, double curl, const NodeCoef<double> &c)
 {
-    return fmat(-c.eH, curl, fmat(-c.eJ, P, c.eP * E));
+    return fmat(-c.eH, curl, fmat(c.eP, E, -Q));
 }
-__device__ __forceinline__ float e_update_plasma_p(float E, double P, float curl, const NodeCoef<float> &c)
+__device__ __forceinline__ float e_update_plasma_q(float E, double Q, float curl, const NodeCoef<float> &c)
 {
-    return fmat(-c.eH, curl, fmat(-c.eJ, (float)P, fmat(c.eP, E, E)));
+    return fmat(-c.eH, curl, fmat(c.eP, E, E) - (float)Q);
+}
+// The same with CH supplied negated (nH = -CH; bit for bit, negation is exact).
+__device__ __forceinline__ double e_update_plasma_qneg(double E, double Q, double curl, double nH, double eP)
+{
+    return fmat(nH, curl, fmat(eP, E, -Q));
 }
 template <typename T>
-__device__ __forceinline__ double p_update(double P, double Eold, const NodeCoef<T> &c)
+__device__ __forceinline__ double q_update(double Q, double Eold, const NodeCoef<T> &c)
 {
-    return __builtin_fma(c.pc, Eold, c.a * P);
+    return __builtin_fma(c.qc, Eold, c.a * Q);
 }
 
 // Plasma node E update.  FP64: CA E - CJ J - CH curl.  FP32: the same in
@@ -293,7 +299,7 @@ __device__ __forceinline__ float j_update_delta(float J, float Eold, float Enew,
 }
 
 // J_new = a J + b1 E_old + b2 E_new in FP64 for both field precisions (the 3D
-// steps; the 1D steps carry P instead, see NodeCoef): eq.(11)'s exp(-nu dt)
+// steps; the 1D steps carry Q instead, see NodeCoef): eq.(11)'s exp(-nu dt)
 // fractions keep their FP64 accuracy; the E values enter already widened.
 template <typename T>
 __device__ __forceinline__ double j_update(double J, double Eold, double Enew, const NodeCoef<T> &c)

@@ -47,9 +47,9 @@ struct Chunk {
     typedef typename JType<JF>::type JT;
     typedef typename RegOf<T, JF>::type R;
     R E[C], H[C];
-    JT J[PLASMA ? C : 1];          // P = J - b2 E in FP64 (the ablation: J itself, in FP32)
+    JT J[PLASMA ? C : 1];          // Q = CJ (J - b2 E) in FP64 (the ablation: J itself, in FP32)
     JT Ed[JF && PLASMA ? C : 1];   // the ablation: E^n, the J update's E_old, kept across steps
-    NodeCoef<R> cf[PLASMA ? C : 1];   // eJ and eH held negated (see chunk_load)
+    NodeCoef<R> cf[PLASMA ? C : 1];   // eH (and in the ablation eJ) held negated (see chunk_load)
     float jc[JF && PLASMA ? 3 * C : 1];   // JF: a-1, b1, b2 of each node rounded to FP32
     R nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
     uint32_t pmask;                // bit i: node i is plasma
@@ -223,7 +223,7 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
         for (int i = 0; i < C; ++i) {
             if (w[i] != 0.0) ck.pmask |= 1u << i;
             ck.cf[i] = node_coef_t<R>(w[i], v[i], g.dt, g.dz, g.scheme);
-            ck.cf[i].eJ = opaque<R>(-ck.cf[i].eJ);
+            if constexpr (JF) ck.cf[i].eJ = opaque<R>(-ck.cf[i].eJ);   // the Q carry needs no CJ
             ck.cf[i].eH = opaque<R>(-ck.cf[i].eH);
             if constexpr (JF) {
                 ck.jc[3 * i] = (float)(ck.cf[i].a - 1.0);
@@ -340,12 +340,12 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck,
         if constexpr (PLASMA && JF) {
             ck.E[i] = e_update_plasma_neg(ck.E[i], ck.J[i], curl, ck.cf[i].eJ, ck.cf[i].eH, ck.cf[i].eA);
         } else if constexpr (PLASMA) {
-            // P^n from E^n before E^n is overwritten, then E^{n+1} from P^{n-1}
-            // (e_update_plasma_p, p_update); the plasma formula reproduces the
+            // Q^n from E^n before E^n is overwritten, then E^{n+1} from Q^{n-1}
+            // (e_update_plasma_q, q_update); the plasma formula reproduces the
             // vacuum update at vacuum nodes
-            const double pn = p_update<R>(ck.J[i], (double)ck.E[i], ck.cf[i]);
-            ck.E[i] = e_update_plasma_neg(ck.E[i], ck.J[i], curl, ck.cf[i].eJ, ck.cf[i].eH, ck.cf[i].eP);
-            ck.J[i] = pn;
+            const double qn = q_update<R>(ck.J[i], (double)ck.E[i], ck.cf[i]);
+            ck.E[i] = e_update_plasma_qneg(ck.E[i], ck.J[i], curl, ck.cf[i].eH, ck.cf[i].eP);
+            ck.J[i] = qn;
         } else {
             ck.E[i] = fmat(ck.nce, curl, ck.E[i]);   // e_update_vac
         }
@@ -355,7 +355,7 @@ __device__ __forceinline__ void chunk_e(Chunk<T, C, PLASMA, CPML, JF> &ck,
 // The ablation's J update (after the source), with E_old the copy of E^n kept
 // from the previous step; at vacuum nodes a*0 + 0*E + 0*E keeps J at +0.  The
 // Mur ends rewrite E after this and leave their copy stale, which is harmless:
-// end nodes carry no plasma (b1 = 0).  (The carried P is advanced inside
+// end nodes carry no plasma (b1 = 0).  (The carried Q is advanced inside
 // chunk_e.)
 template <typename T, int C, bool PLASMA, bool CPML, bool JF = false>
 __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML, JF> &ck)
@@ -372,7 +372,7 @@ __device__ __forceinline__ void chunk_j(Chunk<T, C, PLASMA, CPML, JF> &ck)
 }
 
 // One time step of a chunk that holds no grid end and no source: H, then E
-// with the carried P (or, in the ablation, E then J).
+// with the carried Q (or, in the ablation, E then J).
 template <typename T, int C, bool PLASMA, bool CPML, bool JF, typename GetEr, typename GetHl>
 __device__ __forceinline__ void chunk_step_plain(Chunk<T, C, PLASMA, CPML, JF> &ck, const Grids &g,
                                                  GetEr get_er, GetHl get_hl)
@@ -467,7 +467,7 @@ __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, En
 }
 
 // One full time step of a wave holding a grid end, the source or a probe: H;
-// E with the carried P (the P update reads E^n first); the source, added to
+// E with the carried Q (the Q update reads E^n first); the source, added to
 // E^{n+1} (eq.(15)); the ablation's J update; then the ends (first-order Mur,
 // or PEC E = 0).  sv: the source value of this step.  Only the parts of the
 // roles in mask RM are compiled in.
