@@ -12,26 +12,48 @@
 
 namespace fdtdp {
 
-template <typename T>
-__device__ __forceinline__ double ld(const T *a, const Grid2 &g, int64_t i, int64_t j)
+// A neighbour of cell k = i ny + j one step along an axis: its index (wrapped
+// on a periodic axis) and whether it exists (false beyond a wall, where the
+// field reads as zero).  The index is always one to load from (the cell itself
+// where the neighbour is absent), so every neighbour load is issued
+// unconditionally, beside the others, and no load waits on a branch.
+struct Nb {
+    int64_t k;
+    bool ok;
+};
+__device__ __forceinline__ Nb nb_jp(const Grid2 &g, int64_t k, int64_t j)
 {
-    // field at (i, j): wrapped on a periodic axis, zero outside a walled one
-    if (i < 0 || i >= g.nx) {
-        if (!g.px) return 0.0;
-        i = i < 0 ? i + g.nx : i - g.nx;
-    }
-    if (j < 0 || j >= g.ny) {
-        if (!g.py) return 0.0;
-        j = j < 0 ? j + g.ny : j - g.ny;
-    }
-    return (double)a[i * g.ny + j];
+    const bool in = j + 1 < g.ny;
+    return {in ? k + 1 : (g.py ? k - (g.ny - 1) : k), in || g.py};
+}
+__device__ __forceinline__ Nb nb_jm(const Grid2 &g, int64_t k, int64_t j)
+{
+    const bool in = j > 0;
+    return {in ? k - 1 : (g.py ? k + (g.ny - 1) : k), in || g.py};
+}
+__device__ __forceinline__ Nb nb_ip(const Grid2 &g, int64_t k, int64_t i)
+{
+    const bool in = i + 1 < g.nx;
+    return {in ? k + g.ny : (g.px ? k - (g.nx - 1) * g.ny : k), in || g.px};
+}
+__device__ __forceinline__ Nb nb_im(const Grid2 &g, int64_t k, int64_t i)
+{
+    const bool in = i > 0;
+    return {in ? k - g.ny : (g.px ? k + (g.nx - 1) * g.ny : k), in || g.px};
+}
+template <typename T>
+__device__ __forceinline__ double ldn(const T *a, const Nb &n)
+{
+    const double v = (double)a[n.k];
+    return n.ok ? v : 0.0;
 }
 
+// The cell of this thread; i is the same for the whole wave (one row).
 __device__ __forceinline__ bool cell_of(const Grid2 &g, int64_t &i, int64_t &j)
 {
     const int64_t bj_n = (g.ny + 63) / 64, bi_n = (g.nx + 3) / 4;
     const int64_t b = xcd_block((int64_t)blockIdx.x, bj_n * bi_n);
-    i = (b / bj_n) * 4 + (threadIdx.x >> 6);
+    i = (b / bj_n) * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     j = (b % bj_n) * 64 + (threadIdx.x & 63);
     return i < g.nx && j < g.ny;
 }
@@ -44,31 +66,33 @@ __global__ __launch_bounds__(256) void k2_h(Grid2 g, Fields2<T> f)
     if (!cell_of(g, i, j)) return;
     const int64_t k = i * g.ny + j;
     const double ch = g.ch;
+    const Nb jp = nb_jp(g, k, j), ip = nb_ip(g, k, i);
     if constexpr (MODE == 0) {
         const T *Ez = f.E[0];
-        const double e = (double)Ez[k];
-        f.H[0][k] = (T)__builtin_fma(-ch, ld(Ez, g, i, j + 1) - e, (double)f.H[0][k]);
-        f.H[1][k] = (T)__builtin_fma(ch, ld(Ez, g, i + 1, j) - e, (double)f.H[1][k]);
+        const double e = (double)Ez[k], ej = ldn(Ez, jp), ei = ldn(Ez, ip);
+        const double hx = (double)f.H[0][k], hy = (double)f.H[1][k];
+        f.H[0][k] = (T)__builtin_fma(-ch, ej - e, hx);
+        f.H[1][k] = (T)__builtin_fma(ch, ei - e, hy);
     } else {
         const T *Ex = f.E[0], *Ey = f.E[1];
-        const double curl = (ld(Ey, g, i + 1, j) - (double)Ey[k]) - (ld(Ex, g, i, j + 1) - (double)Ex[k]);
-        f.H[0][k] = (T)__builtin_fma(-ch, curl, (double)f.H[0][k]);
+        const double eyi = ldn(Ey, ip), exj = ldn(Ex, jp), hz = (double)f.H[0][k];
+        const double curl = (eyi - (double)Ey[k]) - (exj - (double)Ex[k]);
+        f.H[0][k] = (T)__builtin_fma(-ch, curl, hz);
     }
 }
 
 // One E component of a cell: eqs.(11)+(12) solved, the source, the wall, then
-// eq.(11); the current and the plasma parameters live on the compact support.
+// eq.(11); the current and the plasma parameters live on the compact support
+// (index pidx, or -1 off it) and come in already read (w, v, J: wp2, nu, J^n).
 template <typename T>
-__device__ __forceinline__ void e_cell(const Grid2 &g, int c, T *Ep, int64_t k, double curl_signed, bool src,
-                                       double sv, bool wall, int64_t pidx)
+__device__ __forceinline__ void e_cell(const Grid2 &g, int c, T *Ep, int64_t k, double Eo, double curl_signed,
+                                       bool src, double sv, bool wall, int64_t pidx, double w, double v, double J)
 {
-    const double Eo = (double)Ep[k];
-    double En, J = 0.0;
+    double En;
     Coef cf;
-    const bool plasma = pidx >= 0 && g.wp2[c][pidx] != 0.0;
+    const bool plasma = pidx >= 0 && w != 0.0;
     if (plasma) {
-        cf = node_coef(g.wp2[c][pidx], g.nu[c][pidx], g.dt, g.d, 0);
-        J = g.J[c][pidx];
+        cf = node_coef(w, v, g.dt, g.d, 0);
         En = __builtin_fma(cf.CH, curl_signed, __builtin_fma(-cf.CJ, J, cf.CA * Eo));
     } else {
         En = __builtin_fma(g.ce, curl_signed, Eo);
@@ -79,27 +103,53 @@ __device__ __forceinline__ void e_cell(const Grid2 &g, int c, T *Ep, int64_t k, 
     Ep[k] = (T)En;
 }
 
-// E^{n+1} and J^{n+1} from H^{n+1/2}; m = n + 1 (the source time).
+// E^{n+1} and J^{n+1} from H^{n+1/2}; m = n + 1 (the source time).  Every load
+// a cell needs (H and its neighbours, E, and on the support wp2, nu and J) is
+// issued before any arithmetic, so a wave waits on one round of loads.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k2_e(Grid2 g, Fields2<T> f, int64_t m)
 {
+    constexpr int NC = MODE == 0 ? 1 : 2;
     int64_t i, j;
     if (!cell_of(g, i, j)) return;
     const int64_t k = i * g.ny + j;
-    const int2 sp = g.span[i];
-    const int64_t pidx = (j >= sp.x && j < sp.y) ? g.rowoff[i] + (j - sp.x) : -1;
+    const int2 sp = g.span[i];                      // the row's support (i is wave-uniform)
+    const int64_t ro = g.rowoff[i];
+    const int64_t pidx = (j >= sp.x && j < sp.y) ? ro + (j - sp.x) : -1;
+    const Nb jm = nb_jm(g, k, j), im = nb_im(g, k, i);
+    double Eo[NC], w[NC], v[NC], J[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        Eo[c] = (double)f.E[c][k];
+        w[c] = v[c] = J[c] = 0.0;
+    }
+    double curl[NC];
+    if constexpr (MODE == 0) {
+        const T *Hx = f.H[0], *Hy = f.H[1];
+        const double hy = (double)Hy[k], hyi = ldn(Hy, im), hx = (double)Hx[k], hxj = ldn(Hx, jm);
+        curl[0] = (hy - hyi) - (hx - hxj);
+    } else {
+        const T *Hz = f.H[0];
+        const double hz = (double)Hz[k], hzj = ldn(Hz, jm), hzi = ldn(Hz, im);
+        curl[0] = hz - hzj;
+        curl[1] = -(hz - hzi);
+    }
+    if (pidx >= 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            w[c] = g.wp2[c][pidx];
+            v[c] = g.nu[c][pidx];
+            J[c] = g.J[c][pidx];
+        }
+    }
     const bool src = g.has_src && i == g.si && j == g.sj;
     const double sv = src ? source_value((double)m * g.dt, g.src_tau, g.src_t0, g.src_amp) : 0.0;
     if constexpr (MODE == 0) {
-        const T *Hx = f.H[0], *Hy = f.H[1];
-        const double curl = ((double)Hy[k] - ld(Hy, g, i - 1, j)) - ((double)Hx[k] - ld(Hx, g, i, j - 1));
         const bool wall = (!g.px && i == 0) || (!g.py && j == 0);
-        e_cell<T>(g, 0, f.E[0], k, curl, src, sv, wall, pidx);
+        e_cell<T>(g, 0, f.E[0], k, Eo[0], curl[0], src, sv, wall, pidx, w[0], v[0], J[0]);
     } else {
-        const T *Hz = f.H[0];
-        const double hz = (double)Hz[k];
-        e_cell<T>(g, 0, f.E[0], k, hz - ld(Hz, g, i, j - 1), false, 0.0, !g.py && j == 0, pidx);
-        e_cell<T>(g, 1, f.E[1], k, -(hz - ld(Hz, g, i - 1, j)), src, sv, !g.px && i == 0, pidx);
+        e_cell<T>(g, 0, f.E[0], k, Eo[0], curl[0], false, 0.0, !g.py && j == 0, pidx, w[0], v[0], J[0]);
+        e_cell<T>(g, 1, f.E[1], k, Eo[1], curl[1], src, sv, !g.px && i == 0, pidx, w[1], v[1], J[1]);
     }
 }
 
