@@ -266,7 +266,6 @@ __device__ __forceinline__ void e_cell(const Geo3 &g, const Plasma3<T> &pl, cons
                                        T hx, T hy, T hz, T hx_j, T hx_k, T hy_i, T hy_k, T hz_i, T hz_j,
                                        T &e0, T &e1, T &e2)
 {
-    const T zero = (T)0;
     T dHz_y = hz - hz_j;
     T dHy_z = hy - hy_k;
     T dHx_z = hx - hx_k;

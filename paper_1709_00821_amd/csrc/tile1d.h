@@ -456,11 +456,26 @@ struct EndCarry {
     T e0, e1, eR, eR1;
 };
 
+// E at node 1 in the lane holding node 0 (register left_reg of lane 0):
+// register left_reg + 1 of the same lane, or, with two nodes a lane and node 0
+// in register 1, the next lane's register 0.  Every lane takes part in the
+// cross-lane move.
+template <typename T, int C>
+__device__ __forceinline__ T node1_of_left(const T (&E)[C], int left_reg)
+{
+    if constexpr (C > 2) {
+        return left_reg ? E[2] : E[1];
+    } else {
+        const T nx = shfl_down1(E[0]);
+        return left_reg ? nx : E[1];
+    }
+}
+
 template <typename T, int C>
 __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, EndCarry<T> &c)
 {
     c.e0 = r.left_reg ? E[1] : E[0];
-    c.e1 = r.left_reg ? E[2] : E[1];
+    c.e1 = node1_of_left<T, C>(E, r.left_reg);
     const int ir = r.right_reg;
     c.eR = upick<T, C>(E, ir);
     c.eR1 = ir ? upick<T, C>(E, ir - 1) : shfl_up1(E[C - 1]);
@@ -488,7 +503,7 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, co
     chunk_j<T, C, PLASMA, CPML, JF>(ck);
     const bool mur = g.bc == 0;
     if constexpr ((RM & kRoleLeft) != 0) {
-        const R en1 = r.left_reg ? ck.E[2] : ck.E[1];
+        const R en1 = node1_of_left<R, C>(ck.E, r.left_reg);
         const R v = mur ? (R)(c.e1 + (R)g.cm * (en1 - c.e0)) : (R)0;
         const bool here = lane == r.left_lane;
         ck.E[0] = (here && !r.left_reg) ? v : ck.E[0];
