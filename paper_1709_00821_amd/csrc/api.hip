@@ -99,7 +99,7 @@ struct fdtd_plasma {
     // device pointers into the workspace
     int64_t *d_off = nullptr, *d_n = nullptr, *d_src = nullptr, *d_probe = nullptr;
     double *d_wp2 = nullptr, *d_nu = nullptr, *d_freqs = nullptr, *d_samp = nullptr,
-           *d_cpml = nullptr, *d_srcv = nullptr;
+           *d_cpml = nullptr, *d_srcv = nullptr, *d_coef = nullptr;
     double2 *d_X = nullptr, *d_Xtmp = nullptr, *d_tw = nullptr;
     void *d_E[2] = {nullptr, nullptr}, *d_H[2] = {nullptr, nullptr}, *d_J[2] = {nullptr, nullptr};
     void *d_psiE[2] = {nullptr, nullptr}, *d_psiH[2] = {nullptr, nullptr};
@@ -181,6 +181,8 @@ struct fdtd_plasma {
         g.probe = d_probe;
         g.wp2 = d_wp2;
         g.nu = d_nu;
+        g.coef = d_coef;
+        g.coef_n = nodes;
         g.samp = d_samp;
         g.batch = batch;
         g.P = P;
@@ -309,6 +311,7 @@ int validate(const fdtd_plasma_desc *d)
 
 struct Plan {
     Layout L;
+    int64_t o_coef = -1;      // the tiles' coefficient table (none in the FP32 ablation)
     int64_t o_off = 0, o_n = 0, o_src = 0, o_probe = 0, o_wp2 = 0, o_nu = 0, o_freqs = 0, o_samp = 0, o_srcv = 0,
             o_X = 0, o_Xtmp = 0, o_tw = 0, o_cpml = 0;
     int64_t o_E[2] = {0, 0}, o_H[2] = {0, 0}, o_J[2] = {0, 0}, o_psiE[2] = {0, 0}, o_psiH[2] = {0, 0};
@@ -522,6 +525,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     p.o_freqs = L.take(8 * F);
     p.o_wp2 = L.take(8 * p.nodes);
     p.o_nu = L.take(8 * p.nodes);
+    if (d->precision != FDTD_F32_DELTA) p.o_coef = L.take(8 * 4 * p.nodes);
     p.o_samp = L.take(8 * d->batch * P * (int64_t)p.SB);
     p.o_srcv = L.take(8 * (int64_t)p.SB);
     p.o_X = L.take(16 * d->batch * P * (int64_t)F);
@@ -933,6 +937,7 @@ int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size
     h->d_freqs = (double *)(w + p.o_freqs);
     h->d_wp2 = (double *)(w + p.o_wp2);
     h->d_nu = (double *)(w + p.o_nu);
+    h->d_coef = p.o_coef >= 0 ? (double *)(w + p.o_coef) : nullptr;
     h->d_samp = (double *)(w + p.o_samp);
     h->d_srcv = (double *)(w + p.o_srcv);
     h->d_X = (double2 *)(w + p.o_X);
@@ -1009,6 +1014,7 @@ int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size
         e = H2D(h->d_rev_tiles, p.rev_tiles.data(), sizeof(Tile) * p.rev_tiles.size());
     if (e != hipSuccess)
         return undo(fail(FDTD_E_DEVICE, "host-to-device copy failed: %s", hipGetErrorString(e)));
+    if (h->d_coef) launch_coef1d(h->grids(), p.nodes, h->d_coef, st);
     if (desc->bc == FDTD_BC_CPML) {
         const double m = desc->cpml_m > 0 ? desc->cpml_m : 3.0;
         const double eta0 = std::sqrt(mu0() / kEps0);

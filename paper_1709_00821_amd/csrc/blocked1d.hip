@@ -289,7 +289,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_resident(Grids g, State<T> s, in
             ck.E[i] = ck.H[i] = (R)0;
             ck.J[i] = 0.0;
         }
-        ck.pmask = 0;
     }
     const WaveRole role = active ? wave_role<C>(g, b, n, wave_lo, wave_hi) : WaveRole{-1, 0, -1, 0, -1, 1};
     auto get_er = [&](R e0) {

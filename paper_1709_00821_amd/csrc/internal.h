@@ -16,6 +16,10 @@ struct Grids {
     const int64_t *probe;   // [batch * P] probe nodes
     const double *wp2;      // [nodes] plasma frequency^2
     const double *nu;       // [nodes] collision frequency
+    const double *coef;     // [4][nodes] the register tiles' step coefficients of every node
+                            // (node_coef_t<double>: eP, -CH, a, qc), built once; null in
+                            // the FP32 ablation, whose tiles build their own
+    int64_t coef_n;         // row length of coef (the padded node count)
     double *samp;           // [batch * P][SB] probe samples of the current window
     int64_t batch;
     int P;                  // probes per grid
@@ -185,6 +189,8 @@ void launch_cpml_table(double *tab, int P, double m, double smax, double dt, hip
 int resident_max_nodes(int C, int waves);
 
 // ---- adjoint (adjoint1d.hip) -----------------------------------------------
+// The register tiles' coefficient table from wp2 and nu (once per create).
+void launch_coef1d(const Grids &g, int64_t total, double *coef, hipStream_t st);
 void launch_adj_coef(const Grids &g, int64_t total, double *tab, hipStream_t st);
 void launch_adj_prepare(const double2 *X, int64_t batch, int P, int F, int probe,
                         const double2 *xref, double2 *G, double *loss, hipStream_t st);

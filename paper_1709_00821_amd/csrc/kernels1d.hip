@@ -324,4 +324,25 @@ void launch_cpml_table(double *tab, int P, double m, double smax, double dt, hip
     hipLaunchKernelGGL(k_cpml_table, dim3((P + 63) / 64), dim3(64), 0, st, tab, P, m, smax, dt);
 }
 
+// The step coefficients every register tile of a plasma class loads instead of
+// rebuilding them from wp2 and nu at each launch (node_coef_t<double>, the
+// values the tiles computed themselves, so every executor keeps its bits):
+// SoA [4][total] of eP, -CH (held negated, as the tiles use it), a, qc.
+__global__ void k_coef1d(Grids g, int64_t total, double *coef)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const NodeCoef<double> c = node_coef_t<double>(g.wp2[i], g.nu[i], g.dt, g.dz, g.scheme);
+    coef[i] = c.eP;
+    coef[total + i] = -c.eH;
+    coef[2 * total + i] = c.a;
+    coef[3 * total + i] = c.qc;
+}
+
+void launch_coef1d(const Grids &g, int64_t total, double *coef, hipStream_t st)
+{
+    if (total > 0)
+        hipLaunchKernelGGL(k_coef1d, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g, total, coef);
+}
+
 }  // namespace fdtdp

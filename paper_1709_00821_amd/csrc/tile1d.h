@@ -52,7 +52,6 @@ struct Chunk {
     NodeCoef<R> cf[PLASMA ? C : 1];   // eH (and in the ablation eJ) held negated (see chunk_load)
     float jc[JF && PLASMA ? 3 * C : 1];   // JF: a-1, b1, b2 of each node rounded to FP32
     R nch, nce;                    // -dt/(mu0 dz), -dt/(eps0 dz)
-    uint32_t pmask;                // bit i: node i is plasma
     R pE[CPML ? C : 1], pH[CPML ? C : 1];
     R bE[CPML ? C : 1], aE[CPML ? C : 1], bH[CPML ? C : 1], aH[CPML ? C : 1];
     uint32_t eZone, hZone;         // bit i: node i has an E / H psi
@@ -202,10 +201,30 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
     ck.nce = opaque<R>(-(R)g.ce);
     load_chunk_as<T, C>(s.E[buf] + off, k0, lim, ck.E);
     load_chunk_as<T, C>(s.H[buf] + off, k0, lim, ck.H);
-    ck.pmask = 0;
-    if constexpr (PLASMA) {
+    if constexpr (PLASMA && !JF && !CPML) {
+        // the step coefficients from the table built at create (the values
+        // node_coef_t gives, -CH already negated); padding and nodes past the
+        // grid's end read zeros and are never stored.  (CPML tiles, which
+        // also hold the psi registers, build theirs below: loading them
+        // would raise the kernel's peak register count past the file.)
+        load_chunk<double, C>(s.J[buf] + off, k0, lim, ck.J);
+        const int64_t N = g.coef_n;
+        double eP[C], nH[C], a[C], qc[C];
+        load_chunk<double, C>(g.coef + off, k0, lim, eP);
+        load_chunk<double, C>(g.coef + N + off, k0, lim, nH);
+        load_chunk<double, C>(g.coef + 2 * N + off, k0, lim, a);
+        load_chunk<double, C>(g.coef + 3 * N + off, k0, lim, qc);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            ck.cf[i].eP = (R)eP[i];
+            ck.cf[i].eH = (R)nH[i];
+            ck.cf[i].a = a[i];
+            ck.cf[i].qc = qc[i];
+        }
+    } else if constexpr (PLASMA) {
+        // built here from wp2 and nu (CPML tiles; the ablation, which carries
+        // J itself with FP32 coefficients)
         if constexpr (JF) {
-            // the ablation's J values are FP32 numbers held in the FP64 arrays
             double Jd[C];
             load_chunk<double, C>(s.J[buf] + off, k0, lim, Jd);
 #pragma unroll
@@ -221,7 +240,6 @@ __device__ __forceinline__ void chunk_load(Chunk<T, C, PLASMA, CPML, JF> &ck, co
         load_chunk<double, C>(g.nu + off, k0, lim, v);
 #pragma unroll
         for (int i = 0; i < C; ++i) {
-            if (w[i] != 0.0) ck.pmask |= 1u << i;
             ck.cf[i] = node_coef_t<R>(w[i], v[i], g.dt, g.dz, g.scheme);
             if constexpr (JF) ck.cf[i].eJ = opaque<R>(-ck.cf[i].eJ);   // the Q carry needs no CJ
             ck.cf[i].eH = opaque<R>(-ck.cf[i].eH);
