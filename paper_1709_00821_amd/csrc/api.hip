@@ -351,6 +351,10 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
             t.out_hi = (int32_t)std::min<int64_t>(n, out + W);
             t.lo = (int32_t)std::max<int64_t>(0, out - p.Kh);
             t.hi = (int32_t)std::min<int64_t>(n, (int64_t)t.lo + L);
+            // a grid's last tile of a grid longer than a tile ends exactly at
+            // node n (more left halo than needed, the same outputs), so node
+            // n-1 always sits in the last register of the last lane
+            if (t.hi == n && n >= L && p.tileW == 1) t.lo = (int32_t)(n - L);
             // node n-1 must not open a wave: its Mur update reads node n-2 by
             // an in-wave move.  Start one node earlier (node -1 reads as zero
             // and is never written); the tile still reaches n (see DESIGN).
@@ -369,8 +373,26 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
             if (d->bc == FDTD_BC_CPML &&
                 (t.lo < d->cpml_cells + 1 || t.hi > n - 2 - d->cpml_cells))
                 fl |= TILE_CPML;
-            t.flags = fl;
             const bool role = (fl & (TILE_LEFT_END | TILE_RIGHT_END | TILE_SOURCE | TILE_PROBE)) != 0;
+            if (role && !(fl & TILE_CPML) && p.tileW == 1) {
+                // the fixed-register role step applies when every role node
+                // sits where it expects it
+                const int C = p.tileC;
+                bool fixed = true;
+                if (fl & TILE_LEFT_END) fixed = fixed && t.lo == 0;
+                if (fl & TILE_RIGHT_END) fixed = fixed && (int64_t)t.lo == n - L;
+                if (fl & TILE_SOURCE) fixed = fixed && (s - t.lo) % C == 0;
+                int np = 0;
+                for (int q = 0; q < d->n_probes; ++q) {
+                    const int64_t pc = d->probe_cells[b * d->n_probes + q];
+                    if (pc >= t.out_lo && pc < t.out_hi) {
+                        ++np;
+                        fixed = fixed && (pc - t.lo) % C == 0;
+                    }
+                }
+                if (fixed && np <= 2) fl |= TILE_FIXED;
+            }
+            t.flags = fl;
             const int k = (fl & TILE_CPML) ? 2 : role ? 3 : (fl & TILE_PLASMA) ? 1 : 0;
             cls[k].push_back(t);
         }
@@ -382,9 +404,18 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
         p.ntiles[k] = (int64_t)cls[k].size();
         for (int r = 0; r < kRoleGroups; ++r) p.group_n[k][r] = 0;
         if (k >= 2 && p.tileW == 1 && p.ntiles[k] >= kRoleGroupMinTiles) {
+            // a group too small to fill the GPU would be one latency-bound
+            // launch more on the side stream: its tiles join the last group,
+            // launched once, each wave taking the code of its own roles
+            int64_t cnt[kRoleGroups] = {};
+            for (const Tile &t : cls[k]) ++cnt[role_group(t.flags)];
+            auto grp = [&](const Tile &t) {
+                const int r = role_group(t.flags);
+                return cnt[r] < kRoleGroupMinLaunch ? kRoleGroups - 1 : r;
+            };
             std::stable_sort(cls[k].begin(), cls[k].end(),
-                             [](const Tile &a, const Tile &b) { return role_group(a.flags) < role_group(b.flags); });
-            for (const Tile &t : cls[k]) ++p.group_n[k][role_group(t.flags)];
+                             [&](const Tile &a, const Tile &b) { return grp(a) < grp(b); });
+            for (const Tile &t : cls[k]) ++p.group_n[k][grp(t)];
         } else {
             p.group_n[k][kRoleGroups - 1] = p.ntiles[k];
         }
@@ -635,12 +666,14 @@ void launch_class(fdtd_plasma *h, const Grids &g, State<T> &s, int cur, int c, i
     int64_t first = h->tile_first[c];
     // an unsplit CPML or role class (below the grouping threshold): one launch
     // whose waves each take the role code of their own group
-    const bool mixed = c >= 2 && h->tileW == 1 && h->group_n[c][kRoleGroups - 1] == h->ntiles[c];
+    // (the last group of a split class is launched the same way: it holds
+    // the tiles of the rarer role combinations)
+    const bool one_wave = c >= 2 && h->tileW == 1;
     for (int r = 0; r < kRoleGroups; ++r) {
         const int64_t n = h->group_n[c][r];
         if (n)
             launch_tiled<T>(g, s, cur, h->d_tiles + first, n, c, h->tileC, nsteps, slot, st, h->tileW,
-                            mixed ? -1 : r);
+                            one_wave && r == kRoleGroups - 1 ? -1 : r);
         first += n;
     }
 }

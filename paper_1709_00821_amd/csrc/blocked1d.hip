@@ -211,6 +211,20 @@ void launch_group(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64
         case -1: return launch_roles<T, C, KLASS, -1>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
         default: break;
         }
+        if constexpr (KLASS == 1) {
+            // the fixed-register role step (TILE_FIXED tiles; role tiles only)
+            constexpr int F = kRoleFixed | kRoleProbe;
+            switch (group) {
+            case 5: return launch_roles<T, C, KLASS, F>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+            case 6: return launch_roles<T, C, KLASS, F | kRoleSrc>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+            case 7: return launch_roles<T, C, KLASS, F | kRoleLeft>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+            case 8: return launch_roles<T, C, KLASS, F | kRoleRight>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+            case 9:
+                return launch_roles<T, C, KLASS, F | kRoleLeft | kRoleSrc>(g, s, cur, tiles, ntiles, nsteps, slot0,
+                                                                           st);
+            default: break;
+            }
+        }
     }
     launch_roles<T, C, KLASS, kRoleAll>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
 }

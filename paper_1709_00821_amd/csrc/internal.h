@@ -69,7 +69,11 @@ enum {
     TILE_SOURCE = 4,      // the grid's source node held
     TILE_PROBE = 8,       // a probe node among the written-back nodes
     TILE_PLASMA = 16,     // some held node has wp2 > 0
-    TILE_CPML = 32        // some held node lies in a CPML layer
+    TILE_CPML = 32,       // some held node lies in a CPML layer
+    TILE_FIXED = 64       // a one-wave role tile whose role nodes sit where the fixed-register
+                          // role step expects them: node 0 at register 0 of lane 0, node n-1 at
+                          // register C-1 of lane 63, the source and at most two probes at
+                          // register 0 of their lanes
 };
 
 // One workgroup of the resident kernel: waves [w0, w1) of a bin hold grid g's
@@ -98,23 +102,29 @@ constexpr int kTileClasses = 4;
 // whose launches are latency bound, take one launch with the full step.  The
 // probe part, and the source part, still check at run time whether the tile
 // has one.
-enum : int { kRoleSrc = 1, kRoleLeft = 2, kRoleRight = 4, kRoleProbe = 8, kRoleAll = 15 };
-constexpr int kRoleGroups = 6;
+// kRoleFixed: the role nodes sit at the registers TILE_FIXED names, so the
+// role step addresses them directly instead of picking registers at run time.
+enum : int { kRoleSrc = 1, kRoleLeft = 2, kRoleRight = 4, kRoleProbe = 8, kRoleAll = 15, kRoleFixed = 16 };
+constexpr int kRoleGroups = 11;
 constexpr int64_t kRoleGroupMinTiles = 2048;
+constexpr int64_t kRoleGroupMinLaunch = 1024;   // smaller groups join the last one
 // group of a tile from its TILE_* flags: probe only, source, left end, right
-// end, left end and source, anything else
+// end, left end and source (0-4), the same five with TILE_FIXED (5-9),
+// anything else (10)
 inline int role_group(int flags)
 {
     const int m = ((flags & TILE_SOURCE) ? kRoleSrc : 0) | ((flags & TILE_LEFT_END) ? kRoleLeft : 0) |
                   ((flags & TILE_RIGHT_END) ? kRoleRight : 0);
+    int r;
     switch (m) {
-    case 0: return 0;
-    case kRoleSrc: return 1;
-    case kRoleLeft: return 2;
-    case kRoleRight: return 3;
-    case kRoleLeft | kRoleSrc: return 4;
-    default: return 5;
+    case 0: r = 0; break;
+    case kRoleSrc: r = 1; break;
+    case kRoleLeft: r = 2; break;
+    case kRoleRight: r = 3; break;
+    case kRoleLeft | kRoleSrc: r = 4; break;
+    default: return kRoleGroups - 1;
     }
+    return (flags & TILE_FIXED) ? r + 5 : r;
 }
 
 // ---- kernel launchers (kernels1d.hip) ------------------------------------

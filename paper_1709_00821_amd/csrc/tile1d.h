@@ -489,9 +489,17 @@ __device__ __forceinline__ T node1_of_left(const T (&E)[C], int left_reg)
     }
 }
 
-template <typename T, int C>
+template <typename T, int C, bool FX = false>
 __device__ __forceinline__ void ends_init(const T (&E)[C], const WaveRole &r, EndCarry<T> &c)
 {
+    if constexpr (FX) {
+        // node 0 in register 0, node n-1 in register C-1 (see TILE_FIXED)
+        c.e0 = E[0];
+        c.e1 = E[1];
+        c.eR = E[C - 1];
+        c.eR1 = E[C - 2];
+        return;
+    }
     c.e0 = r.left_reg ? E[1] : E[0];
     c.e1 = node1_of_left<T, C>(E, r.left_reg);
     const int ir = r.right_reg;
@@ -514,13 +522,22 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, co
                                            GetEr get_er, GetHl get_hl)
 {
     typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
+    constexpr bool FX = RM > 0 && (RM & kRoleFixed) != 0;
     chunk_h<T, C, PLASMA, CPML, JF>(ck, get_er(ck.E[0]));
     chunk_e<T, C, PLASMA, CPML, JF>(ck, get_hl(ck.H[C - 1]));
-    if constexpr ((RM & kRoleSrc) != 0)
+    if constexpr ((RM & kRoleSrc) != 0 && FX) {
+        ck.E[0] = lane == r.src_lane ? add_source<R>(ck.E[0], sv) : ck.E[0];
+    } else if constexpr ((RM & kRoleSrc) != 0) {
         uput<R, C>(ck.E, r.src_reg, lane == r.src_lane, add_source<R>(upick<R, C>(ck.E, r.src_reg), sv));
+    }
     chunk_j<T, C, PLASMA, CPML, JF>(ck);
     const bool mur = g.bc == 0;
-    if constexpr ((RM & kRoleLeft) != 0) {
+    if constexpr ((RM & kRoleLeft) != 0 && FX) {
+        const R v = mur ? (R)(c.e1 + (R)g.cm * (ck.E[1] - c.e0)) : (R)0;
+        c.e1 = ck.E[1];
+        ck.E[0] = lane == r.left_lane ? v : ck.E[0];
+        c.e0 = v;
+    } else if constexpr ((RM & kRoleLeft) != 0) {
         const R en1 = node1_of_left<R, C>(ck.E, r.left_reg);
         const R v = mur ? (R)(c.e1 + (R)g.cm * (en1 - c.e0)) : (R)0;
         const bool here = lane == r.left_lane;
@@ -529,7 +546,13 @@ __device__ __forceinline__ void chunk_step(Chunk<T, C, PLASMA, CPML, JF> &ck, co
         c.e0 = v;
         c.e1 = en1;
     }
-    if constexpr ((RM & kRoleRight) != 0) {
+    if constexpr ((RM & kRoleRight) != 0 && FX) {
+        const R en1 = ck.E[C - 2];
+        const R v = mur ? (R)(c.eR1 + (R)g.cm * (en1 - c.eR)) : (R)0;
+        ck.E[C - 1] = lane == r.right_lane ? v : ck.E[C - 1];
+        c.eR = v;
+        c.eR1 = en1;
+    } else if constexpr ((RM & kRoleRight) != 0) {
         const int ir = r.right_reg;
         const R prev = shfl_up1(ck.E[C - 1]);
         const R left1 = upick<R, C>(ck.E, ir > 0 ? ir - 1 : 0);
@@ -617,9 +640,10 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
                                          int64_t phi, int nsteps, int slot0, GetEr er, GetHl hl, Post post)
 {
     constexpr bool SRC = (RM & kRoleSrc) != 0;
+    constexpr bool FX = RM > 0 && (RM & kRoleFixed) != 0;
     typedef typename Chunk<T, C, PLASMA, CPML, JF>::R R;
     EndCarry<R> c;
-    ends_init<R, C>(ck.E, r, c);
+    ends_init<R, C, FX>(ck.E, r, c);
     for (int base = 0; base < nsteps; base += 64) {
         const int cnt = nsteps - base < 64 ? nsteps - base : 64;
         const int slot = slot0 + base;
@@ -633,6 +657,10 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
             chunk_step<T, C, PLASMA, CPML, RM, JF>(ck, g, r, lane, c, sv, er, hl);
             post(base + st);
             if constexpr ((RM & kRoleProbe) == 0) {
+            } else if constexpr (FX) {
+                // at most two probes, each in register 0 of its lane
+                if (wp.n > 0 && lane == wp.lane[0]) g.samp[wp.row[0] + slot + st] = (double)ck.E[0];
+                if (wp.n > 1 && lane == wp.lane[1]) g.samp[wp.row[1] + slot + st] = (double)ck.E[0];
             } else if (wp.n > 2) {
                 wave_probes<R, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
             } else {
