@@ -230,6 +230,26 @@ def test_role_groups_bitwise(G, precision):
                 assert np.array_equal(Ft[b][k], Fb[0][k]), (b, k)
 
 
+def test_fixed_register_role_tiles_bitwise(G):
+    """Slabs laid out like the 4096-slab batch (source 32 nodes in, probes 16
+    nodes from either end, every slab longer than a tile): each slab's last
+    tile ends at its last node and every role tile has its roles at fixed
+    registers, so they run the fixed-register role step (and groups too
+    small for a launch of their own run in the mixed launch).  FP64: the
+    bits of the per-step path."""
+    slabs = W.batch_c4(n_slabs=1100, lmin=400, lmax=1400, n_freqs=4, steps=200)
+    T = 200
+    say(f"case fixed-register role tiles slabs={len(slabs)} steps={T}")
+    kw = dict(tile_cells=512, steps_per_pass=48)
+    Xt, Ft = gpu_run(G, slabs, T, "f64", "tiled", **kw)
+    Xs, Fs = gpu_run(G, slabs, T, "f64", "step")
+    assert np.array_equal(Xt, Xs)
+    for b in range(0, len(slabs), 29):
+        for k in ("E", "H", "J"):
+            assert np.array_equal(Ft[b][k], Fs[b][k]), (b, k)
+    assert np.max(np.abs(Xt)) > 0
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32d"])
 def test_exec_modes_bitwise_identical(G, precision):
     rng = np.random.default_rng(21)
