@@ -145,7 +145,8 @@ int fdtd_plasma_workspace_bytes(const fdtd_plasma_desc *desc, size_t *bytes);
 
 /*
  * Validate the descriptor, lay out the workspace, copy the host arrays to the
- * device (on desc->stream) and zero the state.  Host arrays are borrowed only
+ * device (on desc->stream), build the per-node coefficients of section II
+ * (eqs.(9), (11), (13) from wp2 and nu) and zero the state.  Host arrays are borrowed only
  * for the duration of the call.  dev_workspace (256-byte aligned device
  * memory of at least fdtd_plasma_workspace_bytes) stays owned by the caller
  * and must outlive the handle; NULL makes the library allocate and own it.
@@ -177,7 +178,9 @@ int fdtd_plasma_create_static(const fdtd_plasma_desc *desc, fdtd_plasma **out);
 
 /*
  * Advance every grid by nsteps (>= 0) time steps, asynchronously on the
- * handle's stream.  In FDTD_F64 and FDTD_F32_DELTA, step(a) followed by
+ * handle's stream.  A step is section II's: H by eq.(14), E by eqs.(11)+(12)
+ * solved together, the eq.(15) source, J by eq.(11), the ends, the probe
+ * samples.  In FDTD_F64 and FDTD_F32_DELTA, step(a) followed by
  * step(b) gives bit-for-bit the same state and spectra as step(a + b); in
  * FDTD_F32 the fields are rounded to FP32 where each launch ends, so the two
  * agree to that rounding.
@@ -185,8 +188,9 @@ int fdtd_plasma_create_static(const fdtd_plasma_desc *desc, fdtd_plasma **out);
 int fdtd_plasma_step(fdtd_plasma *h, int64_t nsteps);
 
 /*
- * Reset fields, currents and spectra to zero at step 0, then advance nsteps,
- * replaying a HIP graph captured on the first call with this nsteps.  With
+ * Reset fields, currents and spectra to zero at step 0, then advance nsteps
+ * (one run of section IV-B's experiment), replaying a HIP graph captured on
+ * the first call with this nsteps.  With
  * FDTD_FLAG_CHECKPOINT the run also stores the forward checkpoints used by
  * fdtd_plasma_grad_r2.
  */
@@ -194,7 +198,8 @@ int fdtd_plasma_run(fdtd_plasma *h, int64_t nsteps);
 
 /*
  * Copy the running DFT to host arrays re, im of [batch][n_probes][n_freqs]
- * doubles, waiting for the stream.  FDTD_E_STATE before any step,
+ * doubles, waiting for the stream: the probe spectra from which section IV-B
+ * forms reflection and transmission (two runs, with and without plasma).  FDTD_E_STATE before any step,
  * FDTD_E_NONFINITE if any value is NaN or Inf (the values are still copied).
  */
 int fdtd_plasma_probe_spectra(fdtd_plasma *h, double *re, double *im);
@@ -220,7 +225,8 @@ int fdtd_plasma_probe_fft(fdtd_plasma *h, int64_t nfft, double *re, double *im);
 
 /*
  * Copy one grid's state to host arrays (doubles, waiting for the stream):
- * E[n], H[n-1] (H at k+1/2), J[n] in A/m^2 (any pointer may be NULL).
+ * the Yee unknowns of eqs.(4)-(6), E[n], H[n-1] (H at k+1/2), and the current
+ * J[n] of eq.(5) in A/m^2 (any pointer may be NULL).
  */
 int fdtd_plasma_get_fields(fdtd_plasma *h, int64_t grid, double *E, double *H, double *J);
 
@@ -231,7 +237,8 @@ int fdtd_plasma_steps_done(fdtd_plasma *h, int64_t *steps);
  * Reflection loss of the current spectra, for every grid b:
  *   L_b = sum_f |R_b(f)|^2,  R_b(f) = (X_b(f) - xref_b(f)) / xref_b(f),
  * X_b the running DFT at probe `probe` (R is the two-run reflection
- * coefficient when xref is the same probe in a plasma-free run).
+ * coefficient of section IV-B when xref is the same probe in a plasma-free
+ * run).
  * xref_re/xref_im: host [batch][n_freqs]; loss: host [batch].  Waits for
  * the stream.  FDTD_E_STATE before any step.
  */

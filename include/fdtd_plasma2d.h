@@ -75,7 +75,8 @@ typedef struct {
 int fdtd2d_workspace_bytes(const fdtd2d_desc *desc, size_t *bytes);
 
 /* Validate, lay out the workspace, copy the host arrays (borrowed for the call
- * only) and zero the state.  workspace: 256-byte aligned device memory of at
+ * only) and zero the state; the per-cell coefficients of eqs.(11)+(12) are
+ * formed in the E pass from wp2 and nu.  workspace: 256-byte aligned device memory of at
  * least fdtd2d_workspace_bytes, owned by the caller and outliving the handle,
  * or NULL (the library allocates and owns it).  On failure *out is NULL.
  * Errors: FDTD_E_INVALID (a field out of range, a NaN or negative wp2/nu,
@@ -83,7 +84,9 @@ int fdtd2d_workspace_bytes(const fdtd2d_desc *desc, size_t *bytes);
  * 1/sqrt(2)), FDTD_E_WORKSPACE, FDTD_E_DEVICE. */
 int fdtd2d_create(const fdtd2d_desc *desc, void *workspace, size_t bytes, fdtd2d **out);
 
-/* Advance nsteps (>= 0), asynchronously on the handle's stream.  step(a)
+/* Advance nsteps (>= 0), asynchronously on the handle's stream: per step the
+ * eq.(14) H pass, then the E/J pass (eqs.(11)+(12), the eq.(15) source, the
+ * walls, eq.(11)), then the probe samples.  step(a)
  * followed by step(b) gives the state and spectra of step(a + b) bit for bit. */
 int fdtd2d_step(fdtd2d *h, int64_t nsteps);
 
@@ -92,7 +95,8 @@ int fdtd2d_step(fdtd2d *h, int64_t nsteps);
  * into the spectra inside the run). */
 int fdtd2d_run(fdtd2d *h, int64_t nsteps);
 
-/* Probe spectra to host re, im [n_probes][n_freqs]; waits for the stream.
+/* Probe spectra to host re, im [n_probes][n_freqs] (the running DFT standing
+ * in for section IV-B's FFT of the probe record); waits for the stream.
  * FDTD_E_STATE before any step or with no probes. */
 int fdtd2d_spectra(fdtd2d *h, double *re, double *im);
 

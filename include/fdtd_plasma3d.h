@@ -103,19 +103,22 @@ int fdtd3d_workspace_bytes(const fdtd3d_desc *desc, size_t *bytes);
 /* Validate desc, lay out the workspace (caller-owned device memory of at least
  * workspace_bytes, 256-byte aligned; NULL: the library allocates and frees it),
  * copy the plasma support, CPML tables, sample points and frequencies to the
- * device and zero the state (step 0).  The host arrays are not kept. */
+ * device, build the per-node coefficients of eqs.(11)+(12) (and the eq.(11)
+ * current fractions) from wp2 and nu, and zero the state (step 0).  The host arrays are not kept. */
 int fdtd3d_create(const fdtd3d_desc *desc, void *workspace, size_t bytes, fdtd3d **out);
 
-/* Advance nsteps on the handle's stream (asynchronous).  step(a); step(b) gives
- * the same bits as step(a + b). */
+/* Advance nsteps on the handle's stream (asynchronous); a step is the
+ * section II step on the lattice: eq.(14) for H, eqs.(11)+(12) for E, the
+ * eq.(15) source, eq.(11) for J, then the sample points.  step(a); step(b)
+ * gives the same bits as step(a + b). */
 int fdtd3d_step(fdtd3d *h, int64_t nsteps);
 
 /* Reset to the zero state at step 0 and advance nsteps; the launches for a
  * given nsteps are captured into a hipGraph once and replayed afterwards. */
 int fdtd3d_run(fdtd3d *h, int64_t nsteps);
 
-/* Spectra of every sample point, host [n_points][n_freqs] each (re, im);
- * synchronizes the stream.  Buffered samples are included without changing
+/* Spectra of every sample point, host [n_points][n_freqs] each (re, im), the
+ * running DFT standing in for section IV-B's FFT; synchronizes the stream.  Buffered samples are included without changing
  * the accumulation order of later steps.  FDTD_E_NONFINITE if any entry is
  * NaN or Inf (the arrays are still written). */
 int fdtd3d_spectra(fdtd3d *h, double *re, double *im);
