@@ -4,7 +4,9 @@ bench.py times (the autotuner's entries):
 * the 2^24-node grid, 20000 steps, FP64 and FP32: spectra and every field
   value against the FP64 oracle run on the source's light cone (outside it
   the fields stay exactly zero for the whole run, so the trimmed run is the
-  full-grid result, and the GPU must hold exact zeros there);
+  full-grid result, and the GPU must hold exact zeros there); and with the
+  source moved next to either CPML end, so that the full-size CPML tiles
+  are compared too;
 * the 4096-slab batch, 8000 steps, in one handle: sampled slabs (first,
   last, shortest, longest, two more) against the oracle run slab by slab.
 """
@@ -112,6 +114,48 @@ def test_c2_full_size_matches_lightcone_oracle(G):
         assert ex <= tol_x and max(eE, eH, eJ) <= tol_f
         for k, lim in (("E", hi), ("H", hi - 1), ("J", hi)):
             assert not np.any(F[k][:lo]) and not np.any(F[k][lim:]), k
+
+
+@pytest.mark.parametrize("end", ["left", "right"])
+def test_c2_full_size_cpml_end_matches_oracle(G, end):
+    """The 2^24-node grid in the tuner's launch shapes with its source moved
+    200 cells from one end and probes 100 cells either side of it: compared
+    at step 420, with the pulse (half a cell a step) inside that end's
+    32-cell CPML, through run() (graph replay), and again at step 1500 after
+    step(), when the CPML has absorbed it and what it reflects has come back
+    past the probes.  The oracle runs the cells within T + 3 of the source
+    plus a 32-cell CPML of its own at the cut: the fields never reach the
+    cut, so it is the same problem, and the full grid must hold exact zeros
+    beyond it."""
+    p = W.large_c2()
+    T1, T2 = 420, 1500
+    P = p.cpml_cells
+    s = 200 if end == "left" else p.n - 201
+    p = p.copy(src_cell=s, probes=np.array([s - 100, s + 100], np.int64))
+    reach = T2 + 3
+    lo, hi = (0, s + reach + P + 1) if end == "left" else (s - reach - P, p.n)
+    q = p.copy(n=hi - lo, wp2=p.wp2[lo:hi].copy(), nu=p.nu[lo:hi].copy(), src_cell=s - lo,
+               probes=p.probes - lo)
+    say(f"case c2 full size, source {s} by the {end} CPML end, steps {T1}+{T2 - T1}, oracle on [{lo}, {hi})")
+    o1 = oracle.run(q, T1)
+    o2 = oracle.run(q, T2 - T1, o1)
+    edge = slice(0, P) if end == "left" else slice(q.n - P, q.n)
+    assert np.max(np.abs(o1["E"][edge])) > 0.5, "the pulse must be inside the CPML at the first check"
+    for prec, tol_x, tol_f in (("f64", 1e-12, 1e-12), ("f32", 2e-6, 2e-5)):
+        tune = TU.pick(prec, p.n)
+        say(f"case c2 full size {end} CPML end {prec} {tune}")
+        with G.FdtdPlasma(p, precision=prec, exec="tiled", **tune) as h:
+            for o, adv in ((o1, lambda: h.run(T1)), (o2, lambda: h.step(T2 - T1))):
+                adv()
+                X = h.spectra()[0]
+                F = h.fields(0)
+                ex = _rel(X, o["X"])
+                eE = _rel(F["E"][lo:hi], o["E"], FLOOR["E"])
+                eH = _rel(F["H"][lo:hi - 1], o["H"][:q.n - 1], FLOOR["H"])
+                say(f"c2 {end} CPML end {prec} @{o['step']}: spectra {ex:.2e} E {eE:.2e} H {eH:.2e}")
+                assert ex <= tol_x and max(eE, eH) <= tol_f
+                for k, lim in (("E", hi), ("H", hi - 1)):
+                    assert not np.any(F[k][:lo]) and not np.any(F[k][lim:]), k
 
 
 def test_c4_full_batch_sampled_slabs_match_oracle(G):
