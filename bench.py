@@ -154,6 +154,7 @@ def batched_leg(precision="f32", n_slabs=4096, T=8000, reps=2):
             "ms": round(ms, 3), "slabs": n_slabs, "nodes": cells, "time_steps": T,
             "precision": precision, "exec": "auto (tiled over the concatenated slabs)",
             "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"],
+            "vacuum_tile_cells": tune.get("vacuum_tile_cells", 0),
             "single_step_equivalent": {"gbs": round(value * 1e6 * ss / 1e9, 1),
                                        "frac_of_hbm_peak": round(value * 1e6 * ss / 1e9 / HBM_PEAK_GBS, 2),
                                        "bytes_per_cell_update": round(ss, 2)},
@@ -458,7 +459,8 @@ def counter_traffic(kernel, precision, tune, cells):
         return None
     if (blk.get("source_sha256") != kernel_source_hash() or blk.get("precision") != precision
             or blk.get("tile_cells") != tune["tile_cells"]
-            or blk.get("steps_per_pass") != tune["steps_per_pass"] or blk.get("cells") != cells):
+            or blk.get("steps_per_pass") != tune["steps_per_pass"] or blk.get("cells") != cells
+            or blk.get("vacuum_tile_cells", 0) != tune.get("vacuum_tile_cells", 0)):
         return None
     k = blk.get("kernels", {}).get(kernel)
     return None if k is None else int(k["traffic_bytes_per_launch"])
@@ -719,6 +721,7 @@ def main():
                                f"seeded sinusoidal wp2 on the middle half, per-cell nu",
                    "cells": cells, "time_steps": T, "exec": "tiled",
                    "tile_cells": tune["tile_cells"], "steps_per_pass": tune["steps_per_pass"],
+                   "vacuum_tile_cells": tune.get("vacuum_tile_cells", 0),
                    "fields": args.precision, "coefficients_dft": "f64"},
         "roofline": rl,
         "hbm_view": hv,
@@ -737,7 +740,8 @@ def main():
         out[prec] = {"value": round(cells * T / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(ms2, 3),
                      "roofline": alu_roofline(prof2, dom2, tune2["steps_per_pass"], prec),
                      "hbm_view": roofline(prof2, prec),
-                     "tile_cells": tune2["tile_cells"], "steps_per_pass": tune2["steps_per_pass"]}
+                     "tile_cells": tune2["tile_cells"], "steps_per_pass": tune2["steps_per_pass"],
+                     "vacuum_tile_cells": tune2.get("vacuum_tile_cells", 0)}
         if prec == "f32d":
             out[prec]["mode"] = ("ablation: FP32 fields with eq.(11) and every coefficient in FP32 "
                                  "(delta form), not the specified FP32 mode")

@@ -133,6 +133,13 @@ typedef struct {
     int32_t record_steps;        /* with FDTD_FLAG_RECORD: steps whose probe samples are kept,
                                     in [1, 2^24]; the FFT takes up to 2 * next_pow2(record_steps + 1)
                                     points.  Costs 8 B + 64 B per probe and step of device memory. */
+    int32_t vacuum_tile_cells;   /* TILED, one-wave tiles: nodes of the tiles whose whole span holds
+                                    vacuum only (no plasma node, grid end, CPML layer, source or
+                                    probe): 64*C for C in 12, 16, 24, 32, wider than tile_cells, so
+                                    the halo recompute costs them less.  The other vacuum tiles then
+                                    run with the plasma tiles (whose step gives vacuum nodes the
+                                    vacuum update's bits).  0 = every tile tile_cells wide.  Not with
+                                    FDTD_F32_DELTA. */
     void *stream;                /* hipStream_t for every launch and copy; NULL = null stream */
 } fdtd_plasma_desc;
 

@@ -64,6 +64,7 @@ class Desc(ctypes.Structure):
         ("checkpoint_steps", ctypes.c_int32),
         ("tile_waves", ctypes.c_int32),
         ("record_steps", ctypes.c_int32),
+        ("vacuum_tile_cells", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

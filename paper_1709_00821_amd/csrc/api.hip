@@ -117,6 +117,7 @@ struct fdtd_plasma {
     int64_t tile_first[kTileClasses] = {0, 0, 0, 0};
     int64_t group_n[kTileClasses][kRoleGroups] = {};
     int tileC = 8, Kh = 16, tileW = 1;
+    int wideC = 0;                 // class-0 tiles are 64 wideC nodes wide (0: tileC)
 
     // resident executor
     ResidentSlot *d_slots = nullptr;
@@ -306,6 +307,14 @@ int validate(const fdtd_plasma_desc *d)
                                    d->steps_per_pass > 64))
         return fail(FDTD_E_INVALID, "steps_per_pass %d: must be 0 or a multiple of 4 in [4, 64]",
                     d->steps_per_pass);
+    if (d->vacuum_tile_cells != 0) {
+        const int v = d->vacuum_tile_cells, t = d->tile_cells ? d->tile_cells : 512;
+        if (v != 768 && v != 1024 && v != 1536 && v != 2048)
+            return fail(FDTD_E_INVALID, "vacuum_tile_cells %d: must be 0, 768, 1024, 1536 or 2048", v);
+        if (v <= t) return fail(FDTD_E_INVALID, "vacuum_tile_cells %d not wider than the tiles (%d)", v, t);
+        if (d->tile_waves > 1 || d->precision == FDTD_F32_DELTA)
+            return fail(FDTD_E_INVALID, "vacuum_tile_cells takes one-wave tiles and FDTD_F64 or FDTD_F32");
+    }
     return FDTD_OK;
 }
 
@@ -330,6 +339,7 @@ struct Plan {
     std::vector<ResidentSlot> slots;
     int64_t nbins = 0;
     int exec = 0, tileC = 8, Kh = 16, tileW = 1, resC = 8, resWaves = 8;
+    int wideC = 0;            // wide vacuum tiles: 64 wideC nodes (0: none)
 };
 
 // Tile tables for the temporally blocked executor: per grid, outputs of width
@@ -340,11 +350,44 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
     const int wave_nodes = p.tileC * 64;
     const int L = p.tileW * wave_nodes;
     const int W = L - 2 * p.Kh;
+    const int Lw = p.wideC * 64, Ww = Lw - 2 * p.Kh;   // wide vacuum tiles (Lw = 0: none)
     std::vector<Tile> cls[kTileClasses];
+    std::vector<int64_t> npl;                           // plasma nodes before node k of the grid
     int64_t o = 0;
     for (int64_t b = 0; b < d->batch; ++b) {
         const int64_t n = d->cells[b];
-        for (int64_t out = 0; !(skip && (*skip)[b]) && out < n; out += W) {
+        const int64_t s = d->src_cell[b];
+        if (Lw) {
+            npl.assign(n + 1, 0);
+            for (int64_t k = 0; k < n; ++k) npl[k + 1] = npl[k] + (d->wp2[o + k] != 0.0);
+        }
+        // a wide tile at outputs [out, out + Ww): its whole span [out - Kh,
+        // out - Kh + Lw) vacuum, off both grid ends and the CPML layers, no
+        // source in it and no probe among its outputs
+        auto wide_ok = [&](int64_t out) {
+            const int64_t lo = out - p.Kh, hi = lo + Lw;
+            if (lo < 1 || hi > n - 1) return false;
+            if (d->bc == FDTD_BC_CPML && (lo < d->cpml_cells + 1 || hi > n - 2 - d->cpml_cells)) return false;
+            if (s >= lo && s < hi) return false;
+            for (int q = 0; q < d->n_probes; ++q) {
+                const int64_t pc = d->probe_cells[b * d->n_probes + q];
+                if (pc >= out && pc < out + Ww) return false;
+            }
+            return npl[hi] == npl[lo];
+        };
+        for (int64_t out = 0; !(skip && (*skip)[b]) && out < n;) {
+            if (Lw && wide_ok(out)) {
+                Tile t{};
+                t.grid = (int32_t)b;
+                t.out_lo = (int32_t)out;
+                t.out_hi = (int32_t)(out + Ww);
+                t.lo = (int32_t)(out - p.Kh);
+                t.hi = (int32_t)(out - p.Kh + Lw);
+                t.flags = 0;
+                cls[0].push_back(t);
+                out += Ww;
+                continue;
+            }
             Tile t{};
             t.grid = (int32_t)b;
             t.out_lo = (int32_t)out;
@@ -362,7 +405,6 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
             int fl = 0;
             if (t.lo <= 0) fl |= TILE_LEFT_END;
             if (t.hi == n) fl |= TILE_RIGHT_END;
-            const int64_t s = d->src_cell[b];
             if (s >= t.lo && s < t.hi) fl |= TILE_SOURCE;
             for (int q = 0; q < d->n_probes; ++q) {
                 const int64_t pc = d->probe_cells[b * d->n_probes + q];
@@ -393,8 +435,11 @@ void build_tiles(const fdtd_plasma_desc *d, Plan &p, const std::vector<char> *sk
                 if (fixed && np <= 2) fl |= TILE_FIXED;
             }
             t.flags = fl;
-            const int k = (fl & TILE_CPML) ? 2 : role ? 3 : (fl & TILE_PLASMA) ? 1 : 0;
+            // with wide vacuum tiles, class 0 holds only those; a narrow
+            // vacuum tile runs with the plasma tiles (same bits)
+            const int k = (fl & TILE_CPML) ? 2 : role ? 3 : ((fl & TILE_PLASMA) || Lw) ? 1 : 0;
             cls[k].push_back(t);
+            out += W;
         }
         o += n;
     }
@@ -498,6 +543,7 @@ int plan(const fdtd_plasma_desc *d, Plan &p)
     // executor choice
     p.tileC = d->tile_cells ? d->tile_cells / 64 : 8;
     p.tileW = d->tile_waves ? d->tile_waves : 1;
+    p.wideC = d->vacuum_tile_cells / 64;
     p.Kh = d->steps_per_pass ? d->steps_per_pass : 48;
     p.resC = 8;
     p.resWaves = 8;   // 512-thread workgroups keep the FP64 coefficients in registers without spills
@@ -672,8 +718,8 @@ void launch_class(fdtd_plasma *h, const Grids &g, State<T> &s, int cur, int c, i
     for (int r = 0; r < kRoleGroups; ++r) {
         const int64_t n = h->group_n[c][r];
         if (n)
-            launch_tiled<T>(g, s, cur, h->d_tiles + first, n, c, h->tileC, nsteps, slot, st, h->tileW,
-                            one_wave && r == kRoleGroups - 1 ? -1 : r);
+            launch_tiled<T>(g, s, cur, h->d_tiles + first, n, c, c == 0 && h->wideC ? h->wideC : h->tileC,
+                            nsteps, slot, st, h->tileW, one_wave && r == kRoleGroups - 1 ? -1 : r);
         first += n;
     }
 }
@@ -910,6 +956,7 @@ int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size
     h->psi_bytes = p.psi_bytes;
     h->exec = p.exec;
     h->tileC = p.tileC;
+    h->wideC = p.wideC;
     h->tileW = p.tileW;
     h->Kh = p.Kh;
     h->resC = p.resC;

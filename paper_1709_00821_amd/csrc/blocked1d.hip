@@ -248,6 +248,17 @@ void launch_tiled_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int
         launch_group<T, C, 1>(g, s, cur, tiles, ntiles, group, nsteps, slot0, st);
 }
 
+// Wide vacuum tiles (class 0 with a vacuum tile width of 1536 or 2048 nodes):
+// the vacuum step only, the other classes are never this wide.
+template <typename T, int C>
+void launch_vacuum_c(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int nsteps,
+                     int slot0, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((ntiles + 3) / 4);
+    hipLaunchKernelGGL((k_tiled<T, C, 0, false>), dim3(nb), dim3(256), 0, st, g, s, cur, tiles, ntiles, nsteps,
+                       slot0);
+}
+
 template <typename T>
 void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64_t ntiles, int klass,
                   int C, int nsteps, int slot0, hipStream_t st, int waves, int group)
@@ -259,6 +270,12 @@ void launch_tiled(const Grids &g, State<T> &s, int cur, const Tile *tiles, int64
     case 4: launch_tiled_c<T, 4>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
     case 8: launch_tiled_c<T, 8>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
     case 12: launch_tiled_c<T, 12>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
+    case 24:
+        if (klass == 0) launch_vacuum_c<T, 24>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+        break;
+    case 32:
+        if (klass == 0) launch_vacuum_c<T, 32>(g, s, cur, tiles, ntiles, nsteps, slot0, st);
+        break;
     default: launch_tiled_c<T, 16>(g, s, cur, tiles, ntiles, klass, nsteps, slot0, st, group); break;
     }
 }

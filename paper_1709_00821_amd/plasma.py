@@ -22,7 +22,7 @@ def _as_list(problems) -> List[Problem1D]:
 
 def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: int = 0,
               steps_per_pass: int = 0, checkpoint: int = 0, stream_handle: int = 0,
-              tile_waves: int = 0, record: int = 0):
+              tile_waves: int = 0, record: int = 0, vacuum_tile_cells: int = 0):
     """Build the C descriptor; returns (desc, arrays it points into)."""
     probs = _as_list(problems)
     p0 = probs[0]
@@ -62,6 +62,7 @@ def make_desc(problems, precision: str = "f64", exec: str = "auto", tile_cells: 
     d.cpml_cells = p0.cpml_cells
     d.tile_cells = tile_cells
     d.tile_waves = tile_waves
+    d.vacuum_tile_cells = vacuum_tile_cells
     d.cpml_m, d.cpml_sigma_max = p0.cpml_m, p0.cpml_sigma_max
     d.steps_per_pass = steps_per_pass
     d.stream = stream_handle or None
@@ -81,7 +82,7 @@ class FdtdPlasma:
     def __init__(self, problems: Union[Problem1D, Sequence[Problem1D]], precision: str = "f64",
                  exec: str = "auto", tile_cells: int = 0, steps_per_pass: int = 0, tile_waves: int = 0,
                  checkpoint: int = 0, stream: Optional[torch.cuda.Stream] = None,
-                 device: Union[int, str, torch.device] = "cuda", record: int = 0):
+                 device: Union[int, str, torch.device] = "cuda", record: int = 0, vacuum_tile_cells: int = 0):
         probs = _as_list(problems)
         self.problems = probs
         self.device = torch.device(device)
@@ -89,7 +90,7 @@ class FdtdPlasma:
         self.cells = np.array([q.n for q in probs], np.int64)
         self.offsets = np.concatenate([[0], np.cumsum(self.cells)])
         d, self._keep = make_desc(probs, precision, exec, tile_cells, steps_per_pass, checkpoint,
-                                  self.stream.cuda_stream, tile_waves, record)
+                                  self.stream.cuda_stream, tile_waves, record, vacuum_tile_cells)
         self.desc = d
         self.precision = precision
         self.workspace_bytes = workspace_bytes(d)

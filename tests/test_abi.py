@@ -91,6 +91,23 @@ def test_bad_tuning_rejected(L):
         assert _code(d)[0] == code
 
 
+def test_vacuum_tile_cells_validated(L):
+    """Wide vacuum tiles: 768, 1024, 1536 or 2048 nodes, wider than the other
+    tiles, one-wave tiles, not in the FP32 delta ablation."""
+    p = W.slab_c1()
+    for kw in ({"vacuum_tile_cells": 1024}, {"vacuum_tile_cells": 2048, "tile_cells": 256},
+               {"vacuum_tile_cells": 768, "precision": "f32"}):
+        d, keep = _desc(p, exec="tiled", **kw)
+        assert _code(d)[0] == 0, kw
+    for kw in ({"vacuum_tile_cells": 1000}, {"vacuum_tile_cells": 512},
+               {"vacuum_tile_cells": 768, "tile_cells": 1024}, {"vacuum_tile_cells": 1024, "tile_waves": 2},
+               {"vacuum_tile_cells": 1024, "precision": "f32d"}):
+        d, keep = _desc(p, exec="tiled", **kw)
+        assert _code(d)[0] == -1, kw
+        assert b"vacuum_tile_cells" in L.lib().fdtd_plasma_last_error() or \
+            b"FDTD_F32_DELTA" in L.lib().fdtd_plasma_last_error()
+
+
 def test_resident_rejects_cpml_and_long_grids(L):
     p = W.slab_c1().copy(bc="cpml", cpml_cells=20, wp2=np.zeros(1000))
     d, keep = _desc(p, exec="resident")

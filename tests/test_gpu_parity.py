@@ -401,6 +401,43 @@ def test_tiled_geometries_bitwise(G, C, K, WV):
         assert np.array_equal(Fs[b]["E"], Ft[b]["E"])
 
 
+def _wide_vacuum_problems():
+    """Grids with long vacuum runs: the plain-run shape at 2^16 nodes (CPML
+    ends, plasma on the middle half), and a batch of Mur slabs whose vacuum
+    sides are several wide tiles long, one of them holding a probe."""
+    big = W.large_c2(n=1 << 16, n_freqs=8)
+    batch = [W.slab_c1(n=n, slab=(lo, lo + 700), src=150, probes=(60, n - 80), n_freqs=8)
+             for n, lo in ((9001, 2500), (4200, 3300), (6143, 300))]
+    return [[big], batch]
+
+
+@pytest.mark.parametrize("C,V,K", [(8, 1024, 56), (4, 2048, 32), (8, 1536, 48), (4, 768, 24)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_wide_vacuum_tiles_bitwise(G, C, V, K, precision):
+    """Wide vacuum tiles (vacuum_tile_cells V) give the bits of the run with
+    every tile 64 C wide at the same steps per launch, in FP64 and FP32
+    storage (whose bits depend on where launches end, the same in both);
+    FP64 also gives the per-step path's bits."""
+    T = 401
+    for probs in _wide_vacuum_problems():
+        say(f"case wide vacuum tiles C={C} V={V} K={K} {precision} lens={[q.n for q in probs]}")
+        Xt, Ft = gpu_run(G, probs, T, precision, "tiled", tile_cells=64 * C, steps_per_pass=K)
+        Xw, Fw = gpu_run(G, probs, T, precision, "tiled", tile_cells=64 * C, steps_per_pass=K,
+                         vacuum_tile_cells=V)
+        with G.FdtdPlasma(probs, precision=precision, exec="tiled", tile_cells=64 * C, steps_per_pass=K,
+                          vacuum_tile_cells=V) as h:
+            assert h.profile(K).get("tiled_vacuum", (0, 0, 0))[2] > 0, "no wide vacuum tile formed"
+        assert np.array_equal(Xt, Xw)
+        for b in range(len(probs)):
+            for k in ("E", "H", "J"):
+                assert np.array_equal(Ft[b][k], Fw[b][k]), (b, k)
+        if precision == "f64":
+            Xs, Fs = gpu_run(G, probs, T, "f64", "step")
+            assert np.array_equal(Xs, Xw)
+            for b in range(len(probs)):
+                assert np.array_equal(Fs[b]["E"], Fw[b]["E"]), b
+
+
 def _edge_problem(case):
     """The regimes the other parity problems do not reach (all on the
     1000-cell slab geometry unless named): a collisionless plasma (nu = 0,
