@@ -64,8 +64,9 @@ enum { FDTD_SCHEME_CONSISTENT = 0, FDTD_SCHEME_PAPER_EQ13 = 1, FDTD_SCHEME_ETD1 
  * each mode agrees with the FP64 result to its own rounding level.
  * STEP:     two launches per time step (H, then E/J/source/ends/probes);
  * TILED:    temporal blocking, steps_per_pass steps per launch on register
- *           tiles of tile_waves waves of tile_cells nodes each, with halo
- *           recompute at the tile ends, ping-pong buffers;
+ *           tiles of tile_waves waves of tile_cells nodes each (tiles whose
+ *           span holds vacuum only: vacuum_tile_cells nodes, if set), with
+ *           halo recompute at the tile ends, ping-pong buffers;
  * RESIDENT: one persistent launch; each workgroup keeps whole grids in
  *           registers for the entire run (short grids, e.g. batches of slabs);
  * MIXED:    per pass, the grids that fit a workgroup run as RESIDENT bins and
