@@ -139,9 +139,12 @@ struct fdtd_plasma {
     bool poisoned = false;
 
     // side stream for the few CPML-touching tiles, which otherwise add their
-    // serial latency to every pass; fork/join through events (capturable)
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // serial latency to every pass; fork/join through events (capturable).
+    // With both CPML and role tiles, the role tiles take a second side stream,
+    // so that on a short grid the pass waits for the longer of the two
+    // latency-bound launches instead of their sum.
+    hipStream_t side = nullptr, side2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
 
     // checkpoints (FDTD_FLAG_CHECKPOINT) and adjoint storage
     int64_t ck_T = 0;          // longest run sized for
@@ -790,7 +793,15 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
             if (fork) {
                 (void)hipEventRecord(h->ev_fork, h->stream);
                 (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
-                for (int c = 2; c < kTileClasses; ++c) launch_class<T>(h, g, s, h->cur, c, (int)k, slot, h->side);
+                if (h->side2) {
+                    (void)hipStreamWaitEvent(h->side2, h->ev_fork, 0);
+                    launch_class<T>(h, g, s, h->cur, 2, (int)k, slot, h->side);
+                    launch_class<T>(h, g, s, h->cur, 3, (int)k, slot, h->side2);
+                    (void)hipEventRecord(h->ev_join2, h->side2);
+                } else {
+                    for (int c = 2; c < kTileClasses; ++c)
+                        launch_class<T>(h, g, s, h->cur, c, (int)k, slot, h->side);
+                }
                 (void)hipEventRecord(h->ev_join, h->side);
             }
             for (int c = 0; c < kTileClasses; ++c)
@@ -799,7 +810,10 @@ int advance_t(fdtd_plasma *h, int64_t nsteps)
                     launch_class<T>(h, g, s, h->cur, c, (int)k, slot, h->stream);
                     prof_end(h);
                 }
-            if (fork) (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
+            if (fork) {
+                (void)hipStreamWaitEvent(h->stream, h->ev_join, 0);
+                if (h->side2) (void)hipStreamWaitEvent(h->stream, h->ev_join2, 0);
+            }
         } else if (h->exec == FDTD_EXEC_MIXED) {
             // bins and tiles hold disjoint grids.  The bins advance the whole
             // window in one launch (beside the tiles on the side stream, unless
@@ -991,8 +1005,10 @@ int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size
 
     auto undo = [&](int code) {
         if (h->side) (void)hipStreamDestroy(h->side);
+        if (h->side2) (void)hipStreamDestroy(h->side2);
         if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
         if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+        if (h->ev_join2) (void)hipEventDestroy(h->ev_join2);
         if (h->owns_ws && h->ws) (void)hipFree(h->ws);
         delete h;
         return code;
@@ -1108,6 +1124,10 @@ int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size
         if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+            return undo(fail(FDTD_E_DEVICE, "side stream creation failed"));
+        if (h->exec == FDTD_EXEC_TILED && h->ntiles[2] > 0 && h->ntiles[3] > 0 &&
+            (hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming) != hipSuccess))
             return undo(fail(FDTD_E_DEVICE, "side stream creation failed"));
     }
     reset(h);
@@ -1544,8 +1564,13 @@ int fdtd_plasma_destroy(fdtd_plasma *h)
         (void)hipStreamSynchronize(h->side);
         (void)hipStreamDestroy(h->side);
     }
+    if (h->side2) {
+        (void)hipStreamSynchronize(h->side2);
+        (void)hipStreamDestroy(h->side2);
+    }
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_join2) (void)hipEventDestroy(h->ev_join2);
     for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : h->adj_graphs) (void)hipGraphExecDestroy(kv.second);
     if (h->owns_ws && h->ws) (void)hipFree(h->ws);

@@ -692,12 +692,23 @@ __device__ __forceinline__ void run_role_any(Chunk<T, C, PLASMA, CPML, JF> &ck, 
 #define FDTDP_ROLE(M) \
     run_role<T, C, PLASMA, CPML, M>(ck, g, r, wp, lane, b, wave_lo, plo, phi, nsteps, slot0, er, hl, post)
     if constexpr (CPML) {
-        // tiles of a CPML class carry the psi registers too: one variant (the
-        // full role step, whose parts are no-ops where the wave lacks the
-        // node); with two or more, the 512-node instantiations spill
-        (void)rm;
-        FDTDP_ROLE(kRoleAll);
-        return;
+        // tiles of a CPML class carry the psi registers too.  At 512 nodes
+        // and more: one variant (the full role step, whose parts are no-ops
+        // where the wave lacks the node); with two or more those
+        // instantiations spill.  At 256 nodes (short grids, where these
+        // latency-bound tiles set the pass time) the two ends alone, the
+        // usual CPML tiles of a grid longer than a few tiles, get their own.
+        if constexpr (C <= 4) {
+            switch (rm) {
+            case kRoleLeft: FDTDP_ROLE(kRoleLeft | kRoleProbe); return;
+            case kRoleRight: FDTDP_ROLE(kRoleRight | kRoleProbe); return;
+            default: FDTDP_ROLE(kRoleAll); return;
+            }
+        } else {
+            (void)rm;
+            FDTDP_ROLE(kRoleAll);
+            return;
+        }
     }
     switch (rm) {
     case 0: FDTDP_ROLE(kRoleProbe); break;

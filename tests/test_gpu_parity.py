@@ -438,6 +438,21 @@ def test_wide_vacuum_tiles_bitwise(G, C, V, K, precision):
                 assert np.array_equal(Fs[b]["E"], Fw[b]["E"]), b
 
 
+@pytest.mark.parametrize("n", [1024, 10240, 61440])
+def test_cpml_end_tiles_bitwise(G, n):
+    """The paper preset (5-cell CPML ends) on 256-node tiles, whose CPML tiles
+    take the step compiled for their one grid end where that is all they
+    hold (and the full role step otherwise: at 1024 cells the left one also
+    holds the source and a probe): the per-step path's bits, FP64."""
+    p = W.paper_preset(steps=700, n=n)
+    say(f"case cpml end tiles n={n}")
+    Xs, Fs = gpu_run(G, [p], 700, "f64", "step")
+    Xt, Ft = gpu_run(G, [p], 700, "f64", "tiled", tile_cells=256, steps_per_pass=64)
+    assert np.array_equal(Xs, Xt)
+    for k in ("E", "H", "J"):
+        assert np.array_equal(Fs[0][k], Ft[0][k]), k
+
+
 def _edge_problem(case):
     """The regimes the other parity problems do not reach (all on the
     1000-cell slab geometry unless named): a collisionless plasma (nu = 0,
