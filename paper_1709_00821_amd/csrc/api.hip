@@ -140,9 +140,11 @@ struct fdtd_plasma {
 
     // side stream for the few CPML-touching tiles, which otherwise add their
     // serial latency to every pass; fork/join through events (capturable).
-    // With both CPML and role tiles, the role tiles take a second side stream,
-    // so that on a short grid the pass waits for the longer of the two
-    // latency-bound launches instead of their sum.
+    // On a short grid with both CPML and role tiles, the role tiles take a
+    // second side stream, so that the pass waits for the longer of the two
+    // latency-bound launches instead of their sum (on a long grid the side
+    // launches hide behind the bulk tiles, and the second stream's extra join
+    // a pass costs more than it saves).
     hipStream_t side = nullptr, side2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
 
@@ -1126,6 +1128,7 @@ int create_impl(const fdtd_plasma_desc *desc, Plan &p, void *dev_workspace, size
             hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
             return undo(fail(FDTD_E_DEVICE, "side stream creation failed"));
         if (h->exec == FDTD_EXEC_TILED && h->ntiles[2] > 0 && h->ntiles[3] > 0 &&
+            h->ntiles[0] + h->ntiles[1] < kSide2MaxBulkTiles &&
             (hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking) != hipSuccess ||
              hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming) != hipSuccess))
             return undo(fail(FDTD_E_DEVICE, "side stream creation failed"));

@@ -94,6 +94,12 @@ constexpr int kTwiddleChunk = 1024;
 // without grid ends, source or probes), 2 tiles touching a CPML layer, 3 the
 // other tiles holding a grid end, the source or a probe.
 constexpr int kTileClasses = 4;
+// The CPML and role classes take a stream each (instead of sharing one) only
+// while the bulk classes hold fewer tiles than one round of the plasma
+// kernel on the GPU (three waves a SIMD): then every launch of a pass is
+// latency bound.  Measured: the 1000-step paper setup at 10,240 cells 0.88 ->
+// 0.60 ms with two streams; the 2^24-node grid 82.6 -> 90.7 ms.
+constexpr int64_t kSide2MaxBulkTiles = 3072;
 
 // Roles a one-wave tile may hold, as bits of a mask.  A CPML or role class
 // with at least kRoleGroupMinTiles tiles is sorted into role groups and each
