@@ -419,15 +419,15 @@ __global__ __launch_bounds__(256) void k_e3d(Geo3 g, Fields3<T> f, Plasma3<T> pl
 
 __device__ __forceinline__ float lane_up1(float x)
 {
-    // lane l receives lane l-1's value, lane 0 receives 0 (DPP wave_shr:1)
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xF, 0xF,
-                                                                 false));
+    // lane l receives lane l-1's value, lane 0 receives 0 (DPP wave_shr:1,
+    // zero written by the move itself)
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double lane_up1(double x)
 {
     const int2 v = __builtin_bit_cast(int2, x);
-    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(0, v.x, 0x138, 0xF, 0xF, false),
-                                                __builtin_amdgcn_update_dpp(0, v.y, 0x138, 0xF, 0xF, false)));
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_mov_dpp(v.x, 0x138, 0xF, 0xF, true),
+                                                __builtin_amdgcn_mov_dpp(v.y, 0x138, 0xF, 0xF, true)));
 }
 
 // What one plane of a fused-kernel lane reads from the input copy.

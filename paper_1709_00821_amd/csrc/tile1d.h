@@ -59,14 +59,16 @@ struct Chunk {
 
 // Whole-wave neighbour moves with DPP (gfx9 wave_shl:1 / wave_shr:1): lane i
 // receives lane i+1's value (down) or lane i-1's (up); the lane with no source
-// receives 0.  One v_mov_b32_dpp per 32-bit half, no LDS crossbar trip.
+// receives 0, written by the move itself (bound_ctrl), so no zeroed
+// destination has to be set up first.  One v_mov_b32_dpp per 32-bit half, no
+// LDS crossbar trip.
 __device__ __forceinline__ int dpp_down1(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int dpp_up1(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true);
 }
 __device__ __forceinline__ float shfl_down1(float x)
 {
