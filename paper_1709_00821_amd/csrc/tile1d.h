@@ -467,6 +467,12 @@ __device__ __forceinline__ double readlane_d(double x, int l)
                                                 __builtin_amdgcn_readlane(v.y, l)));
 }
 
+// acc with lane l set to x (x and l wave-uniform; a select, bit for bit).
+__device__ __forceinline__ double writelane_d(double acc, double x, int l, int lane)
+{
+    return lane == l ? x : acc;
+}
+
 // The end values the Mur updates read, E^n at nodes 0, 1 and n-1, n-2, held
 // from one step to the next: each equals what the previous step wrote (the
 // end node) or read (its neighbour, which later sub-steps of that step leave
@@ -631,8 +637,11 @@ __device__ __forceinline__ void wave_probes(const Grids &g, int b, int64_t wave_
 // nsteps full steps of a wave that holds a grid end, the source or a probe
 // (sample slots slot0 .. slot0 + nsteps - 1 of the window), in runs of up to
 // 64 steps.  The only load is at the start of a run: the source values of its
-// steps, one per lane of the window's table, broadcast from lane st.  Inside a
-// run the wave issues nothing but the probe stores, which it never waits on.
+// steps, one per lane of the window's table, broadcast from lane st.  The
+// samples of up to two probes are gathered the other way round: step st's
+// sample goes into lane st of a register, and the run ends with one
+// coalesced store a probe, so the steps themselves issue no store and change
+// no exec mask (a wave with more probes stores each sample as it is taken).
 // (Every cross-lane read here takes a value all lanes computed: a value
 // computed only in some lanes would be stale in the lane that is read.)
 template <typename T, int C, bool PLASMA, bool CPML, int RM = kRoleAll, bool JF = false, typename GetEr,
@@ -654,6 +663,7 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
             const int i = slot + lane;
             svl = g.srcv[i < g.SB ? i : g.SB - 1];
         }
+        double pb0 = 0.0, pb1 = 0.0;   // the run's samples of probes 0 and 1, lane st: step st
         auto one = [&](int st) {
             const double sv = (SRC && r.src_lane >= 0) ? readlane_d(svl, st) : 0.0;
             chunk_step<T, C, PLASMA, CPML, RM, JF>(ck, g, r, lane, c, sv, er, hl);
@@ -661,13 +671,15 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
             if constexpr ((RM & kRoleProbe) == 0) {
             } else if constexpr (FX) {
                 // at most two probes, each in register 0 of its lane
-                if (wp.n > 0 && lane == wp.lane[0]) g.samp[wp.row[0] + slot + st] = (double)ck.E[0];
-                if (wp.n > 1 && lane == wp.lane[1]) g.samp[wp.row[1] + slot + st] = (double)ck.E[0];
+                if (wp.n > 0) pb0 = writelane_d(pb0, readlane_d((double)ck.E[0], wp.lane[0]), st, lane);
+                if (wp.n > 1) pb1 = writelane_d(pb1, readlane_d((double)ck.E[0], wp.lane[1]), st, lane);
             } else if (wp.n > 2) {
                 wave_probes<R, C>(g, b, wave_lo, plo, phi, lane, ck.E, slot + st);
             } else {
-                if (wp.n > 0) wave_probe_store<R, C>(g, wp.lane[0], wp.reg[0], wp.row[0], lane, ck.E, slot + st);
-                if (wp.n > 1) wave_probe_store<R, C>(g, wp.lane[1], wp.reg[1], wp.row[1], lane, ck.E, slot + st);
+                if (wp.n > 0)
+                    pb0 = writelane_d(pb0, readlane_d((double)upick<R, C>(ck.E, wp.reg[0]), wp.lane[0]), st, lane);
+                if (wp.n > 1)
+                    pb1 = writelane_d(pb1, readlane_d((double)upick<R, C>(ck.E, wp.reg[1]), wp.lane[1]), st, lane);
             }
         };
         int st = 0;
@@ -676,6 +688,12 @@ __device__ __forceinline__ void run_role(Chunk<T, C, PLASMA, CPML, JF> &ck, cons
             one(st + 1);
         }
         if (st < cnt) one(st);
+        if constexpr ((RM & kRoleProbe) != 0) {
+            if (FX || wp.n <= 2) {
+                if (wp.n > 0 && lane < cnt) g.samp[wp.row[0] + slot + lane] = pb0;
+                if (wp.n > 1 && lane < cnt) g.samp[wp.row[1] + slot + lane] = pb1;
+            }
+        }
     }
 }
 
